@@ -1,0 +1,179 @@
+"""Benchmark of the pair-counting hot path on one MI355X.
+
+Workload (one "step"): the r-mu DD pair count of 1e6 clustered points
+(1e4 Gaussian blobs of 100 points, sigma 5, in an open 2000^3 box), r in
+[0, 200) with 40 bins and mu in [0, 1] with 50 bins, line of sight z:
+  1. build the cell list from device-resident float64 positions,
+  2. count the autocorrelation with FP32 separations and the FP64 re-test of
+     every pair inside a rounding band of a decision (bit-exact counts),
+  3. leave the uint64 counts in device memory.
+The metric is candidate pair evaluations per second (the cell-list pairs the
+kernel evaluates), counted only when the counts are bit-exact; the FP64
+counter is timed the same way for the speedup.
+
+Prints one JSON line. Run with --gpus 1 (the only supported value).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_LANE_OPS = 256 * 64 * 2.4e9     # unpacked VALU lane-instructions/s (256 CUs, 2.4 GHz)
+I_ALG_RMU_Z = 21                      # algorithmic FP32 lane-ops per r-mu pair evaluation
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(d, target_s=15.0):
+    """The CPU oracle (brute force, every pair) on a bounded prefix of the
+    same data catalog; its rate is reported in the same unit."""
+    import oracle
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        threads = os.cpu_count() or 1
+    threads = max(1, min(threads, 16))
+    re_, me = np.arange(41) * 5.0, np.arange(51) / 50.0
+    ob = oracle.Binning(oracle.RMU, re_, me, los=oracle.LOS_Z)
+    n = 20000
+    t = time.perf_counter()
+    oracle.count_pairs(d.head(n), None, ob, nthreads=threads)
+    dt = time.perf_counter() - t
+    rate = n * (n - 1) / 2 / max(dt, 1e-9)
+    n2 = int(min(len(d), math.sqrt(2 * rate * target_s)))
+    t = time.perf_counter()
+    oracle.count_pairs(d.head(n2), None, ob, nthreads=threads)
+    dt = time.perf_counter() - t
+    pairs = n2 * (n2 - 1) / 2
+    return {"value": pairs / dt / 1e9, "unit": "Gpair-evals/s", "cores": threads, "kind": "oracle",
+            "sample": "brute-force DD (all %d pairs) of the first %d points of the same clustered "
+                      "catalog, same r-mu binning, %.1f s" % (pairs, n2, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import catalogs
+    import paper_1210_1833_amd as cute
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    d, _ = catalogs.config2()
+    n = len(d)
+    xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (d.x, d.y, d.z)]
+    bn = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(51) / 50.0, los=cute.LOS_Z)
+    counts = torch.zeros(bn.nbins, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    def step(prec):
+        g = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0)
+        _, st = cute.count_pairs(g, None, bn, prec, out=counts, with_stats=True)
+        g.close()
+        return st
+
+    def run(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step(prec) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, sts
+
+    log("bench: r-mu DD, n=%d, FP32_EDGE %d steps" % (n, args.steps))
+    dt32, st32 = run(cute.PREC_FP32_EDGE, args.steps, args.warmup)
+    c32 = counts.cpu().numpy().astype(np.uint64)
+    log("bench: FP64 %d steps" % args.fp64_steps)
+    dt64, st64 = run(cute.PREC_FP64, args.fp64_steps, 1)
+    c64 = counts.cpu().numpy().astype(np.uint64)
+
+    exact = bool(np.array_equal(c32, c64))
+    golden = os.path.join(ROOT, "tests", "golden", "c2_dd_rmu.json")
+    oracle_checked = False
+    if os.path.exists(golden):
+        with open(golden) as f:
+            g = json.load(f)
+        if g["sha256"] == catalogs.sha256_of(d):
+            exact = exact and bool(np.array_equal(c32, np.array(g["counts"], dtype=np.uint64)))
+            oracle_checked = True
+
+    evals = st32[-1]["pair_evals"]
+    in_range = int(c32.sum())
+    ms32 = dt32 / args.steps * 1e3
+    ms64 = dt64 / args.fp64_steps * 1e3
+    value = evals / (ms32 * 1e-3) / 1e9 if exact else 0.0
+    kern_ms = float(np.mean([s["ms_count"] for s in st32]))
+    kern64_ms = float(np.mean([s["ms_count"] for s in st64]))
+    achieved = evals * I_ALG_RMU_Z / (kern_ms * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+
+    out = {
+        "metric": "Gpair-evals/s (bit-exact counts), DD r-mu N=1e6; FP32+edge vs FP64 speedup",
+        "value": round(value, 3),
+        "unit": "Gpair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (+f64 edge re-test)",
+        "data": "synthetic",
+        "config": {
+            "workload": "r-mu DD of 1e6 clustered points (1e4 Gaussian blobs x 100, sigma 5) in an "
+                        "open 2000^3 box; r<200 in 40 bins x mu in [0,1] in 50 bins; LOS z; "
+                        "cell list + FP32 separations with FP64 edge re-test",
+            "n_points": n,
+            "step": "cute_build_grid + cute_count_pairs (auto), inputs resident in HBM",
+            "precision": "FP32_EDGE",
+        },
+        "bit_exact": exact,
+        "checked_against": "oracle golden counts" if oracle_checked else "GPU FP64 path",
+        "pair_evals_per_step": int(evals),
+        "pairs_in_range_per_step": in_range,
+        "retests_per_step": int(st32[-1]["retests"]),
+        "fp32_only_miscounts_per_step": int(st32[-1]["flips"]),
+        "pairs_in_range_per_s": in_range / (ms32 * 1e-3),
+        "brute_force_equiv_pairs_per_s": n * (n - 1) / 2 / (ms32 * 1e-3),
+        "fp64": {"ms_per_step": round(ms64, 4), "kernel_ms": round(kern64_ms, 4),
+                 "gpair_evals_per_s": round(st64[-1]["pair_evals"] / (ms64 * 1e-3) / 1e9, 3)},
+        "speedup_fp32edge_vs_fp64": round(ms64 / ms32, 3),
+        "kernel_speedup_fp32edge_vs_fp64": round(kern64_ms / kern_ms, 3),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                     "unit": "Tlane-op/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(d)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

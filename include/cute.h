@@ -1,0 +1,191 @@
+/*
+ * cute.h - C ABI of the MI355X (gfx950) binned pair counter.
+ *
+ * The library computes the pair-count histograms DD, DR and RR that the
+ * two-point correlation estimators of Alonso, "CUTE solutions for two-point
+ * correlation functions from large cosmological datasets" (arXiv:1210.1833),
+ * are built from:
+ *
+ *   N_p(bin) = number of pairs (i, j), i != j, whose separation falls in bin
+ *                                                   (Sec. 2.2, eq. for N_p^d)
+ *
+ * for the isotropic separation r, the (r, mu) and (sigma, pi) coordinates of
+ * Sec. 2.1 (pi = r mu, sigma = sqrt(r^2 - pi^2)) and the angle theta on the
+ * sphere (cos theta = n1 . n2, Sec. 2.1). Candidate pairs are restricted by a
+ * cell list ("chaining mesh") around each cell, or by spherical pixels for
+ * the angle (Sec. 3.3). The counts feed the natural, Landy-Szalay and
+ * periodic-box estimators (Sec. 2.2) and the Legendre multipoles (Sec. 2.1).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a cute_status and never aborts or exits. A
+ *    failed call leaves its outputs unspecified and sets a thread-local
+ *    message readable with cute_last_error().
+ *  - Coordinates are float64 SoA arrays. Positions are comoving 3-D
+ *    coordinates with the observer at the origin; for CUTE_GEOM_SPHERE they
+ *    are unit vectors.
+ *  - Bins are half-open [e_k, e_{k+1}); the last mu bin is closed at mu = 1.
+ *  - An autocorrelation (b == NULL or b == a) counts each unordered pair i < j
+ *    once and never i == j; a cross-correlation counts all n_a * n_b pairs.
+ *    With these conventions the Landy-Szalay coefficient (N_r - 1)/N_d of
+ *    Sec. 2.2 is exact.
+ *  - Counts are exact: every pair is classified by the same FP64 squared-edge
+ *    predicates as a plain FP64 double loop (mu, pi and sigma through
+ *    products, theta through the chord 2 sin(theta/2)); the FP32 fast path
+ *    re-tests in FP64 every pair within a proven rounding band of a decision.
+ *  - Pointers are host pointers unless a flag below says otherwise. The
+ *    caller owns every array it passes; the library owns grids.
+ *  - All device work of a call is issued on the given stream (NULL = the
+ *    null stream) and the call returns after that work has finished.
+ */
+#ifndef CUTE_H
+#define CUTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CUTE_OK = 0,
+    CUTE_E_INVALID_ARG = 1,   /* bad pointer, size, edge table or geometry    */
+    CUTE_E_UNSUPPORTED = 2,   /* valid request this library does not handle   */
+    CUTE_E_OUT_OF_MEMORY = 3, /* a device or host allocation failed           */
+    CUTE_E_DEVICE = 4,        /* a HIP call failed (no GPU, launch failure)   */
+    CUTE_E_INTERNAL = 5       /* an internal consistency check failed         */
+} cute_status;
+
+typedef enum {
+    CUTE_GEOM_BOX_PERIODIC = 0, /* cube [0, L)^3, minimum-image separations
+                                   (the periodic estimator of Sec. 2.2)      */
+    CUTE_GEOM_BOX_OPEN = 1,     /* open catalog; cells cover its bounding box */
+    CUTE_GEOM_SPHERE = 2        /* unit vectors; pixels in (cos theta, phi),
+                                   the "spherical cubes" of Sec. 3.3          */
+} cute_geometry;
+
+typedef enum {
+    CUTE_BIN_MONO = 0,    /* r                                   (Sec. 2.1) */
+    CUTE_BIN_RMU = 1,     /* r outer, mu = |cos| in [0,1] inner  (Sec. 2.1) */
+    CUTE_BIN_SIGMAPI = 2, /* sigma outer, pi inner               (Sec. 2.1) */
+    CUTE_BIN_THETA = 3    /* angle theta in radians              (Sec. 2.1) */
+} cute_bin_kind;
+
+typedef enum {
+    CUTE_LOS_Z = 0,        /* line of sight along +z (plane-parallel)        */
+    CUTE_LOS_MIDPOINT = 1  /* along p + q, observer at the origin            */
+} cute_los;
+
+typedef enum {
+    CUTE_PREC_FP64 = 0,      /* every pair classified in FP64                 */
+    CUTE_PREC_FP32_EDGE = 1, /* FP32 separations; pairs inside the rounding
+                                band of an edge are re-tested in FP64. Same
+                                counts as CUTE_PREC_FP64.                     */
+    CUTE_PREC_FP32_ONLY = 2  /* FP32 decisions only, no re-test (not exact;
+                                for measuring the FP32 miscount rate)         */
+} cute_precision;
+
+typedef enum {
+    CUTE_EST_NATURAL = 0, /* N_r(N_r-1)/(N_d(N_d-1)) DD/RR - 1    (Sec. 2.2) */
+    CUTE_EST_LS = 1,      /* Landy-Szalay                         (Sec. 2.2) */
+    CUTE_EST_BOX = 2      /* periodic box, uniform expectation    (Sec. 2.2) */
+} cute_estimator;
+
+typedef struct {
+    cute_geometry geom;
+    double box_size;   /* L (CUTE_GEOM_BOX_PERIODIC only); points in [0, L)  */
+    double r_max;      /* largest separation (radians for SPHERE) the grid
+                          will be counted at; 0 = unknown. Used to size cells
+                          and, for a periodic box, to keep the stencil free
+                          of duplicate images.                                */
+    double cell_size;  /* cell side (pixel side in radians for SPHERE);
+                          0 = chosen by the library                           */
+    int32_t device_ptrs; /* nonzero: x, y, z are device pointers             */
+} cute_grid_params;
+
+typedef struct {
+    cute_bin_kind kind;
+    cute_los los;             /* RMU: Z or MIDPOINT; SIGMAPI: MIDPOINT       */
+    int32_t n1;               /* bins of r | sigma | theta                   */
+    const double* edges1;     /* n1+1 strictly increasing, >= 0, finite;
+                                 theta in radians, <= pi                      */
+    int32_t n2;               /* bins of mu | pi; 0 for MONO and THETA       */
+    const double* edges2;     /* n2+1 strictly increasing; mu within [0, 1]  */
+} cute_binning;
+
+typedef struct {
+    uint64_t pair_evals;      /* candidate pairs evaluated by the kernels    */
+    uint64_t pairs_in_range;  /* sum of the counts                           */
+    uint64_t retests;         /* pairs re-tested in FP64 (FP32_EDGE)         */
+    uint64_t flips;           /* re-tested pairs whose FP32 decision differed
+                                 from the FP64 one (the FP32-only miscounts) */
+    uint64_t tiles;           /* home tiles processed                        */
+    double ms_count;          /* device time of the counting launch(es)      */
+} cute_count_stats;
+
+typedef struct {
+    int64_t n;                /* points                                      */
+    int32_t dims[3];          /* cells per axis (SPHERE: phi, cos theta, 1)  */
+    double cell[3];           /* cell sides                                  */
+    double origin[3];         /* lower corner of cell (0, 0, 0)              */
+    double ms_build;          /* device time of the build                    */
+} cute_grid_info;
+
+typedef struct cute_grid cute_grid;
+
+/* Build the cell list of Sec. 3.3 over n points: cells of side a (or pixels
+ * of the sphere) are assigned, the points are sorted by cell, and sorted
+ * FP64 and origin-shifted FP32 copies plus cell offsets are kept on the
+ * device. x, y, z: n float64 each (host, or device if p->device_ptrs).
+ * n may be 0. *out receives a new grid on success (free with cute_free_grid).
+ * Errors: CUTE_E_INVALID_ARG for NULL pointers, n < 0 or n >= 2^31,
+ * non-finite coordinates, periodic coordinates outside [0, L), vectors that
+ * are not unit length (|v|^2 - 1 > 1e-6) for SPHERE, a non-positive L or a
+ * negative cell size; CUTE_E_OUT_OF_MEMORY / CUTE_E_DEVICE from HIP. */
+cute_status cute_build_grid(const double* x, const double* y, const double* z, int64_t n,
+                            const cute_grid_params* p, void* stream, cute_grid** out);
+
+/* Release a grid (NULL is accepted). The grid must not be in use. */
+void cute_free_grid(cute_grid* g);
+
+/* Describe a grid. */
+cute_status cute_get_grid_info(const cute_grid* g, cute_grid_info* info);
+
+/* Pair counts of Sec. 2.2 between grids a and b.
+ * b == NULL or b == a: autocorrelation of a (pairs i < j, Sec. 2.2).
+ * counts: n1 * max(n2, 1) uint64, row-major with edges1 outer, OVERWRITTEN
+ * (a device pointer if counts_on_device != 0). st may be NULL.
+ * Errors: CUTE_E_INVALID_ARG for bad edges, THETA on a non-SPHERE grid or a
+ * 3-D kind on a SPHERE grid, grids of different geometry, a periodic r_max
+ * >= L/2 or a periodic grid too coarse for r_max (rebuild it with r_max set);
+ * CUTE_E_UNSUPPORTED for SIGMAPI with LOS_Z and MIDPOINT in a periodic box. */
+cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_binning* bins,
+                             cute_precision prec, uint64_t* counts, int32_t counts_on_device,
+                             cute_count_stats* st, void* stream);
+
+/* Estimator of Sec. 2.2 per bin (xi has the shape of the counts).
+ * NATURAL: dd, rr; LS: dd, dr, rr; BOX: dd only (MONO binning, periodic
+ * volume box_size^3, expected count N(N-1)/2 * V_shell / L^3 with the exact
+ * shell volume). nd, nr >= 2. A bin whose denominator is 0 gives NaN.
+ * NATURAL and LS evaluate their numerator and denominator exactly in 128-bit
+ * integers and divide once. */
+cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, const uint64_t* dr,
+                             const uint64_t* rr, int64_t nd, int64_t nr,
+                             const cute_binning* bins, double box_size, double* xi);
+
+/* Legendre multipoles of Sec. 2.1 from xi(r, mu) on an RMU binning:
+ * xi_l(r_i) = (2l+1) int_0^1 xi(r_i, mu) P_l(mu) dmu, xi constant within each
+ * mu bin. ells: n_ell even, non-negative degrees. out: n_ell * n1, row-major
+ * with l outer. */
+cute_status cute_xi_multipoles(const double* xi_rmu, const cute_binning* bins, int32_t n_ell,
+                               const int32_t* ells, double* out);
+
+const char* cute_status_string(cute_status s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cute_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTE_H */

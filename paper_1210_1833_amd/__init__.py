@@ -1,0 +1,282 @@
+"""Python binding of the MI355X pair-count library (``libcute.so``).
+
+Argument marshalling only: every step of the counting path runs in the HIP
+kernels behind the C ABI declared in ``include/cute.h``. PyTorch is used only
+for device memory and streams. Importing works without a GPU; the first call
+that needs the library raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcute.so")
+
+# enums of cute.h
+OK, E_INVALID_ARG, E_UNSUPPORTED, E_OUT_OF_MEMORY, E_DEVICE, E_INTERNAL = range(6)
+GEOM_BOX_PERIODIC, GEOM_BOX_OPEN, GEOM_SPHERE = range(3)
+BIN_MONO, BIN_RMU, BIN_SIGMAPI, BIN_THETA = range(4)
+LOS_Z, LOS_MIDPOINT = range(2)
+PREC_FP64, PREC_FP32_EDGE, PREC_FP32_ONLY = range(3)
+EST_NATURAL, EST_LS, EST_BOX = range(3)
+
+EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
+            "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
+
+
+class CuteError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("cute status %d: %s" % (status, msg))
+        self.status = status
+
+
+class GridParams(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_int), ("box_size", ctypes.c_double),
+                ("r_max", ctypes.c_double), ("cell_size", ctypes.c_double),
+                ("device_ptrs", ctypes.c_int32)]
+
+
+class CBinning(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("los", ctypes.c_int),
+                ("n1", ctypes.c_int32), ("edges1", ctypes.POINTER(ctypes.c_double)),
+                ("n2", ctypes.c_int32), ("edges2", ctypes.POINTER(ctypes.c_double))]
+
+
+class CountStats(ctypes.Structure):
+    _fields_ = [("pair_evals", ctypes.c_uint64), ("pairs_in_range", ctypes.c_uint64),
+                ("retests", ctypes.c_uint64), ("flips", ctypes.c_uint64),
+                ("tiles", ctypes.c_uint64), ("ms_count", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dims", ctypes.c_int32 * 3),
+                ("cell", ctypes.c_double * 3), ("origin", ctypes.c_double * 3),
+                ("ms_build", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libcute.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcute.so is not built: run paper_1210_1833_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    lib.cute_build_grid.restype = ctypes.c_int
+    lib.cute_build_grid.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(GridParams), vp,
+                                    ctypes.POINTER(vp)]
+    lib.cute_free_grid.restype = None
+    lib.cute_free_grid.argtypes = [vp]
+    lib.cute_get_grid_info.restype = ctypes.c_int
+    lib.cute_get_grid_info.argtypes = [vp, ctypes.POINTER(GridInfo)]
+    lib.cute_count_pairs.restype = ctypes.c_int
+    lib.cute_count_pairs.argtypes = [vp, vp, ctypes.POINTER(CBinning), ctypes.c_int, vp,
+                                     ctypes.c_int32, ctypes.POINTER(CountStats), vp]
+    lib.cute_xi_estimate.restype = ctypes.c_int
+    lib.cute_xi_estimate.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.POINTER(CBinning), ctypes.c_double, dp]
+    lib.cute_xi_multipoles.restype = ctypes.c_int
+    lib.cute_xi_multipoles.argtypes = [dp, ctypes.POINTER(CBinning), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), dp]
+    lib.cute_status_string.restype = ctypes.c_char_p
+    lib.cute_status_string.argtypes = [ctypes.c_int]
+    lib.cute_last_error.restype = ctypes.c_char_p
+    lib.cute_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load()
+        raise CuteError(rc, "%s (%s)" % (lib.cute_status_string(rc).decode(),
+                                         lib.cute_last_error().decode()))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # pragma: no cover - torch without ROCm
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+@dataclass
+class Binning:
+    """Edges of a binning (cute_binning). edges2 is None for MONO and THETA."""
+    kind: int
+    edges1: np.ndarray
+    edges2: np.ndarray | None = None
+    los: int = LOS_Z
+
+    def __post_init__(self):
+        self.edges1 = np.ascontiguousarray(self.edges1, dtype=np.float64)
+        if self.edges2 is not None:
+            self.edges2 = np.ascontiguousarray(self.edges2, dtype=np.float64)
+
+    @property
+    def shape(self):
+        n1 = len(self.edges1) - 1
+        return (n1,) if self.edges2 is None else (n1, len(self.edges2) - 1)
+
+    @property
+    def nbins(self):
+        return int(np.prod(self.shape))
+
+    def c(self) -> CBinning:
+        b = CBinning()
+        b.kind, b.los = int(self.kind), int(self.los)
+        b.n1 = len(self.edges1) - 1
+        b.edges1 = self.edges1.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if self.edges2 is None:
+            b.n2 = 0
+            b.edges2 = ctypes.POINTER(ctypes.c_double)()
+        else:
+            b.n2 = len(self.edges2) - 1
+            b.edges2 = self.edges2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return b
+
+
+class Grid:
+    """A cell list built on the device (cute_build_grid); freed on deletion."""
+
+    def __init__(self, handle, n, keep=None):
+        self._h = handle
+        self.n = n
+        self._keep = keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> GridInfo:
+        gi = GridInfo()
+        _check(load().cute_get_grid_info(self._h, ctypes.byref(gi)))
+        return gi
+
+    def close(self):
+        if self._h:
+            load().cute_free_grid(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _coords(pos):
+    """(x, y, z, n, device_ptrs, keepalive) from torch tensors or numpy data."""
+    try:
+        import torch
+    except Exception:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(pos, torch.Tensor):
+        t = pos.contiguous()
+        if t.dtype != torch.float64 or t.dim() != 2 or t.shape[1] != 3:
+            raise ValueError("positions must be a float64 tensor of shape (n, 3)")
+        cols = [t[:, k].contiguous() for k in range(3)]
+        dev = 1 if t.is_cuda else 0
+        return cols[0].data_ptr(), cols[1].data_ptr(), cols[2].data_ptr(), t.shape[0], dev, cols
+    if isinstance(pos, (tuple, list)) and len(pos) == 3 and torch is not None and \
+            isinstance(pos[0], torch.Tensor):
+        cols = [c.contiguous() for c in pos]
+        if any(c.dtype != torch.float64 for c in cols):
+            raise ValueError("coordinates must be float64")
+        dev = 1 if cols[0].is_cuda else 0
+        return cols[0].data_ptr(), cols[1].data_ptr(), cols[2].data_ptr(), cols[0].shape[0], dev, cols
+    if hasattr(pos, "x") and hasattr(pos, "y") and hasattr(pos, "z"):
+        cols = [np.ascontiguousarray(getattr(pos, k), dtype=np.float64) for k in "xyz"]
+    else:
+        a = np.asarray(pos, dtype=np.float64)
+        cols = [np.ascontiguousarray(a[:, k]) for k in range(3)]
+    return (cols[0].ctypes.data, cols[1].ctypes.data, cols[2].ctypes.data, len(cols[0]), 0, cols)
+
+
+def build_grid(pos, geom: int, box_size: float = 0.0, r_max: float = 0.0,
+               cell_size: float = 0.0, stream=None) -> Grid:
+    """cute_build_grid. ``pos``: (n, 3) float64 numpy/torch (host or device),
+    a (x, y, z) triple of tensors, or an object with x, y, z arrays."""
+    lib = load()
+    x, y, z, n, dev, keep = _coords(pos)
+    p = GridParams(int(geom), float(box_size), float(r_max), float(cell_size), int(dev))
+    h = ctypes.c_void_p()
+    _check(lib.cute_build_grid(x, y, z, int(n), ctypes.byref(p), _stream_handle(stream),
+                               ctypes.byref(h)))
+    return Grid(h, int(n), keep if dev else None)
+
+
+def count_pairs(a: Grid, b: Grid | None, binning: Binning, prec: int = PREC_FP32_EDGE,
+                out=None, stream=None, with_stats: bool = False):
+    """cute_count_pairs. Returns uint64 counts shaped like the binning (numpy),
+    or fills ``out`` (a torch uint64/int64 device tensor of nbins) in place."""
+    lib = load()
+    cb = binning.c()
+    st = CountStats()
+    if out is None:
+        counts = np.zeros(binning.nbins, dtype=np.uint64)
+        ptr, on_dev = counts.ctypes.data, 0
+    else:
+        counts = out
+        ptr, on_dev = out.data_ptr(), 1
+    rc = lib.cute_count_pairs(a.handle, None if b is None else b.handle, ctypes.byref(cb),
+                              int(prec), ptr, on_dev, ctypes.byref(st), _stream_handle(stream))
+    _check(rc)
+    res = counts.reshape(binning.shape) if out is None else counts
+    return (res, st.as_dict()) if with_stats else res
+
+
+def xi_estimate(estimator: int, dd, dr, rr, nd: int, nr: int, binning: Binning,
+                box_size: float = 0.0):
+    """cute_xi_estimate (host arithmetic in the library)."""
+    lib = load()
+    cb = binning.c()
+
+    def u64(v):
+        return None if v is None else np.ascontiguousarray(v, dtype=np.uint64).reshape(-1)
+
+    ddd, drr, rrr = u64(dd), u64(dr), u64(rr)
+    xi = np.empty(binning.nbins, dtype=np.float64)
+    _check(lib.cute_xi_estimate(int(estimator), ddd.ctypes.data,
+                                None if drr is None else drr.ctypes.data,
+                                None if rrr is None else rrr.ctypes.data,
+                                int(nd), int(nr), ctypes.byref(cb), float(box_size),
+                                xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return xi.reshape(binning.shape)
+
+
+def xi_multipoles(xi_rmu, binning: Binning, ells=(0, 2, 4)):
+    """cute_xi_multipoles: xi_l(r) for even l from an RMU xi(r, mu) table."""
+    lib = load()
+    cb = binning.c()
+    x = np.ascontiguousarray(xi_rmu, dtype=np.float64).reshape(-1)
+    e = np.ascontiguousarray(ells, dtype=np.int32)
+    out = np.empty((len(e), binning.shape[0]), dtype=np.float64)
+    _check(lib.cute_xi_multipoles(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(cb), len(e),
+                                  e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out

@@ -1,0 +1,131 @@
+// Internal structures shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "cute.h"
+
+namespace cute {
+
+// FP64 copy of a sorted point (the raw caller coordinates).
+struct alignas(32) P64 {
+    double x, y, z, w;
+};
+
+// Kinds of pair classification the kernels are specialised for.
+enum Mode : int { M_MONO = 0, M_RMU_Z = 1, M_RMU_MID = 2, M_SIGMAPI = 3, M_THETA = 4 };
+// How a bin index is estimated from the squared separation.
+enum Est : int { E_LIN = 0, E_LOG = 1 };
+// Precision path.
+enum Prec : int { P_FP64 = 0, P_FP32E = 1, P_FP32O = 2 };
+
+// A home tile: a run of sorted points inside one row of cells.
+struct Tile {
+    uint32_t start, end;  // sorted point range [start, end)
+    uint32_t row;         // row index (cy + ny * cz; SPHERE: band)
+    uint32_t c0c1;        // first cell (low 16 bits) and last cell (high 16 bits) along x
+};
+
+// Device-side description of a grid.
+struct GridView {
+    const float4* p32;        // sorted, origin-shifted FP32 (x - c, y - c, z - c, 0)
+    const P64* p64;           // sorted FP64 raw coordinates
+    const uint32_t* cstart;   // cell offsets, ncells + 1
+    int nx, ny, nz;           // cells per axis (SPHERE: phi cells, bands, 1)
+    double ox, oy, oz;        // lower corner of cell (0,0,0) (SPHERE: phi0 = 0, zmin)
+    double ax, ay, az;        // cell sides (SPHERE: dphi, dz)
+    double cx, cy, cz;        // FP32 origin
+};
+
+struct cute_grid_impl;
+
+// Everything a count kernel needs, passed by value.
+struct CountArgs {
+    GridView A, B;
+    const Tile* tiles;
+    uint32_t ntiles;
+    uint32_t* work_head;            // next tile to pop (global counter)
+    unsigned long long* counts;     // nbins global uint64 counts
+    unsigned long long* stats;      // [0] pair evals, [1] retests, [2] flips, [3] tiles
+    int geom;                       // cute_geometry
+    int is_auto;
+    int periodic;
+    double L;
+    double Rs;                      // stencil radius (with margin); SPHERE: chord
+    double th_s;                    // SPHERE: angular stencil radius (radians)
+    double sin_th_s;                // SPHERE: sin(th_s)
+    int n1, n2, nbins;
+    int copies;                     // LDS histogram copies per wave (power of two)
+    int hist_words;                 // nbins * copies
+    uint32_t flush_budget;          // per-wave candidate pairs between flushes
+    // FP32 geometry constants
+    float offx, offy, offz;         // FP32(cA - cB), added to home points (open boxes)
+    float lcx, lcy, lcz;            // FP32(2 cB): l = home_eff + q + lc (midpoint LOS)
+    // dimension-1 estimate: k = clamp(int(fma(t, e1a, e1b)), 0, n1-1)
+    float e1a, e1b;
+    // dimension-2 estimate (mu or pi), linear in mu (or pi)
+    float e2a, e2b;
+    int d2_generic;                 // dimension-2 edges are not linear
+    int d2_partial;                 // mu range is not [0, 1] with a closed top, or pi starts > 0
+    // FP32 decision constants
+    float out_lo, out_hi;           // dim 1 is clean-out if v < out_lo or v >= out_hi
+    float bot32, top32;             // FP32-rounded T1[0], T1[n1] (tentative decisions)
+    float d2lo32, d2hi32;           // FP32-rounded T2[0], T2[n2]
+    float nlo2_first, nhi2_last;    // -T2f[0] (or +BIG), -T2f[n2] (or -BIG) for dim-2 range
+    // rounding band of the ratio predicates (mu, pi, sigma), per pair:
+    //   delta = ll (A2 v + A1 r + A0) + |l| (B2 v + B1 r + B0) + C2 v
+    // with ll = |l|^2 = 1 and |l| = 0 for the z line of sight
+    //   + C2 v + C0
+    float dA0, dA1, dA2, dB0, dB1, dB2, dC2, dC0;  // mu (RMU) or pi (SIGMAPI)
+    float sA0, sA1, sA2, sB0, sB1, sB2, sC2, sC0;  // sigma (SIGMAPI)
+    // tables (global; staged into LDS)
+    const float2* band1;            // n1 entries: (lo_k, hi_{k+1}) FP32 band thresholds of dim 1
+    const float2* band2;            // n2 entries: (-T2f[k] or +BIG, -T2f[k+1] or -BIG)
+    const double* T1;               // n1+1 canonical FP64 thresholds of dim 1
+    const double* T2;               // n2+1 canonical FP64 thresholds of dim 2
+    int mu_top_closed;              // last mu edge == 1
+};
+
+// Host-side grid object.
+struct GridHost {
+    int device;
+    cute_geometry geom;
+    int64_t n;
+    double L;
+    int nx, ny, nz;
+    double ox, oy, oz, ax, ay, az;
+    double cx, cy, cz;
+    double ext;          // max |x - c| over points and axes (FP32 rounding scale)
+    double rawmax;       // max |raw coordinate|
+    double lmax;         // max |p| over points (for |p + q| bounds)
+    float4* p32;
+    P64* p64;
+    uint32_t* cstart;
+    double ms_build;
+    GridView view() const;
+};
+
+// error reporting
+void set_error(const std::string& msg);
+cute_status fail(cute_status s, const std::string& msg);
+
+// exclusive scan of n uint32 values on the device (in may equal out)
+cute_status exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, hipStream_t s);
+
+// home tiles of grid g (runs of <= 64 points in one row, x-extent <= max_w
+// cells); *tiles is a stream-ordered allocation owned by the caller
+cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
+                        uint32_t* ntiles);
+
+// persistent count launch; *grid_used receives the number of workgroups
+cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int wg_waves,
+                         size_t lds_bytes, hipStream_t stream, int* grid_used);
+
+}  // namespace cute
+
+struct cute_grid {
+    cute::GridHost h;
+};

@@ -1,0 +1,115 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/cute.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1210_1833_amd as cute
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "cute.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cute_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(cute.library_path()):
+        pytest.fail("libcute.so is not built (run __graft_entry__.build())")
+    return cute.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared_functions()
+    assert set(cute.EXPORTED) == set(declared), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.cute_status_string(s)
+    assert lib.cute_status_string(99) == b"unknown status"
+
+
+def test_build_grid_rejects_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    p = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0)
+    x = np.zeros(4)
+    # NULL output
+    assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
+                               None, None) == cute.E_INVALID_ARG
+    # negative n
+    assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, -1, ctypes.byref(p),
+                               None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    # NULL coordinates
+    assert lib.cute_build_grid(None, None, None, 4, ctypes.byref(p), None,
+                               ctypes.byref(h)) == cute.E_INVALID_ARG
+    # periodic box without a size, and r_max >= L/2
+    pp = cute.GridParams(cute.GEOM_BOX_PERIODIC, 0.0, 0.0, 0.0, 0)
+    assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pp),
+                               None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    pp = cute.GridParams(cute.GEOM_BOX_PERIODIC, 10.0, 5.0, 0.0, 0)
+    assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pp),
+                               None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    # unknown geometry and negative cell size
+    pg = cute.GridParams(7, 0.0, 0.0, 0.0, 0)
+    assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pg),
+                               None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    pc = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, -1.0, 0)
+    assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pc),
+                               None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    assert lib.cute_last_error()
+
+
+def test_count_and_estimators_reject_bad_binnings(lib):
+    counts = np.zeros(4, dtype=np.uint64)
+    good = cute.Binning(cute.BIN_MONO, [0.0, 1.0, 2.0])
+    # NULL grid
+    assert lib.cute_count_pairs(None, None, ctypes.byref(good.c()), 0, counts.ctypes.data, 0,
+                                None, None) == cute.E_INVALID_ARG
+    bad = [
+        cute.Binning(cute.BIN_MONO, [0.0, 2.0, 1.0]),               # not increasing
+        cute.Binning(cute.BIN_MONO, [-1.0, 1.0]),                   # negative
+        cute.Binning(cute.BIN_MONO, [0.0, np.inf]),                 # not finite
+        cute.Binning(cute.BIN_RMU, [0.0, 1.0], [0.0, 1.5]),         # mu above 1
+        cute.Binning(cute.BIN_THETA, [0.0, 4.0]),                   # theta above pi
+        cute.Binning(cute.BIN_MONO, [0.0, 1.0], [0.0, 1.0]),        # n2 for MONO
+    ]
+    dd = np.ones(4, dtype=np.uint64)
+    xi = np.zeros(4)
+    for b in bad:
+        rc = lib.cute_xi_estimate(cute.EST_NATURAL, dd.ctypes.data, None, dd.ctypes.data, 10, 10,
+                                  ctypes.byref(b.c()), 0.0,
+                                  xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        assert rc == cute.E_INVALID_ARG
+    sp = cute.Binning(cute.BIN_SIGMAPI, [0.0, 1.0], [0.0, 1.0], los=cute.LOS_Z)
+    rc = lib.cute_xi_estimate(cute.EST_NATURAL, dd.ctypes.data, None, dd.ctypes.data, 10, 10,
+                              ctypes.byref(sp.c()), 0.0,
+                              xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert rc == cute.E_UNSUPPORTED
+    # LS without DR, BOX on a non-MONO binning, too-small catalogs
+    rmu = cute.Binning(cute.BIN_RMU, [0.0, 1.0], [0.0, 1.0])
+    assert lib.cute_xi_estimate(cute.EST_LS, dd.ctypes.data, None, dd.ctypes.data, 10, 10,
+                                ctypes.byref(good.c()), 0.0,
+                                xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == cute.E_INVALID_ARG
+    assert lib.cute_xi_estimate(cute.EST_BOX, dd.ctypes.data, None, None, 10, 10,
+                                ctypes.byref(rmu.c()), 100.0,
+                                xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == cute.E_INVALID_ARG
+    assert lib.cute_xi_estimate(cute.EST_NATURAL, dd.ctypes.data, None, dd.ctypes.data, 1, 10,
+                                ctypes.byref(good.c()), 0.0,
+                                xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == cute.E_INVALID_ARG
+    # odd multipole degree
+    ells = np.array([1], dtype=np.int32)
+    out = np.zeros(1)
+    assert lib.cute_xi_multipoles(xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(rmu.c()), 1,
+                                  ells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == cute.E_INVALID_ARG

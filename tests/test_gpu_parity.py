@@ -1,0 +1,252 @@
+"""GPU parity: the HIP pair counter (through the C ABI) against the CPU FP64
+oracle, element by element on the same seeded inputs.
+
+Counts are integers, so the bar is bit-exact equality for FP64 and FP32_EDGE.
+FP32_ONLY is not exact; its miscounts are bounded by the flips that the
+FP32_EDGE path reports (each misclassified pair moves one count)."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import catalogs
+import oracle
+import paper_1210_1833_amd as cute
+from oracle import estimators as est
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EXACT = [cute.PREC_FP64, cute.PREC_FP32_EDGE]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    cute.load()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ocat(c):
+    return c
+
+
+def obin(kind, e1, e2=None, los=cute.LOS_Z, periodic=False, L=0.0):
+    ok = {cute.BIN_MONO: oracle.MONO, cute.BIN_RMU: oracle.RMU, cute.BIN_SIGMAPI: oracle.SIGMAPI,
+          cute.BIN_THETA: oracle.THETA}[kind]
+    ol = oracle.LOS_Z if los == cute.LOS_Z else oracle.LOS_MID
+    return oracle.Binning(ok, e1, e2, los=ol, periodic=periodic, L=L)
+
+
+def gpu_counts(a, b, binning, prec, geom, L=0.0, r_max=0.0, cell=0.0, stats=False):
+    ga = cute.build_grid(a, geom, box_size=L, r_max=r_max, cell_size=cell)
+    gb = None if b is None else cute.build_grid(b, geom, box_size=L, r_max=r_max, cell_size=cell)
+    return cute.count_pairs(ga, gb, binning, prec, with_stats=stats)
+
+
+def check_case(name, a, b, kind, e1, e2=None, los=cute.LOS_Z, geom=cute.GEOM_BOX_OPEN, L=0.0,
+               cell=0.0, precs=EXACT, prune=False):
+    bn = cute.Binning(kind, e1, e2, los=los)
+    rmax = oracle.rmax(obin(kind, e1, e2, los))
+    want = oracle.count_pairs(a, b, obin(kind, e1, e2, los, geom == cute.GEOM_BOX_PERIODIC, L),
+                              prune=prune).reshape(bn.shape)
+    assert want.sum() > 0 or len(a) < 2
+    for prec in precs:
+        say("case %s prec %d n_a %d n_b %s" % (name, prec, len(a), None if b is None else len(b)))
+        got, st = gpu_counts(a, b, bn, prec, geom, L=L,
+                             r_max=(bn.edges1[-1] if kind == cute.BIN_THETA else rmax),
+                             cell=cell, stats=True)
+        assert got.dtype == np.uint64
+        np.testing.assert_array_equal(got, want, err_msg="%s prec %d" % (name, prec))
+        assert st["pairs_in_range"] == int(want.sum())
+    return want
+
+
+# ---------------------------------------------------------------------------
+def test_mono_periodic_auto_and_cross():
+    a = catalogs.uniform_box(6000, 300.0, seed=101)
+    b = catalogs.mixed_periodic(5000, 300.0, seed=102)
+    e = np.linspace(0.0, 45.0, 16)
+    check_case("mono-periodic-auto", a, None, cute.BIN_MONO, e, geom=cute.GEOM_BOX_PERIODIC, L=300.0)
+    check_case("mono-periodic-cross", a, b, cute.BIN_MONO, e, geom=cute.GEOM_BOX_PERIODIC, L=300.0)
+
+
+def test_mono_periodic_config1_full_size():
+    """Config 1 at its full size, against the oracle's brute force."""
+    with open(os.path.join(GOLDEN, "c1_dd_mono.json")) as f:
+        g = json.load(f)
+    c = catalogs.config1()
+    assert catalogs.sha256_of(c) == g["sha256"]
+    bn = cute.Binning(cute.BIN_MONO, np.array(g["r_edges"]))
+    for prec in EXACT:
+        say("case config1 prec", prec)
+        got = gpu_counts(c, None, bn, prec, cute.GEOM_BOX_PERIODIC, L=1000.0, r_max=150.0)
+        np.testing.assert_array_equal(got, np.array(g["counts"], dtype=np.uint64))
+
+
+@pytest.mark.parametrize("cell", [0.0, 7.0, 33.0])
+def test_mono_open_log_bins(cell):
+    d, r = catalogs.config2(n_centres=120, per_blob=40, n_rand=8000, box=250.0)
+    e = np.geomspace(0.2, 40.0, 21)
+    check_case("mono-open-log-auto-%g" % cell, d, None, cute.BIN_MONO, e, cell=cell)
+    check_case("mono-open-log-cross-%g" % cell, d, r, cute.BIN_MONO, e, cell=cell)
+
+
+def test_rmu_z_dd_dr_rr():
+    d, r = catalogs.config2(n_centres=150, per_blob=40, n_rand=15000, box=300.0)
+    re_, me = np.linspace(0, 40, 9), np.linspace(0, 1, 11)
+    check_case("rmu-dd", d, None, cute.BIN_RMU, re_, me)
+    check_case("rmu-dr", d, r, cute.BIN_RMU, re_, me)
+    check_case("rmu-rr", r, None, cute.BIN_RMU, re_, me)
+
+
+def test_rmu_z_partial_mu_range_and_rmin():
+    d, r = catalogs.config2(n_centres=100, per_blob=30, n_rand=6000, box=200.0)
+    check_case("rmu-partial", d, r, cute.BIN_RMU, np.linspace(2, 30, 8), np.linspace(0.1, 0.9, 9))
+
+
+def test_rmu_midpoint_and_sigmapi_lightcone():
+    d, r = catalogs.config3(n_data=6000, n_rand=9000, ra_max_deg=5.0, dec_max_deg=4.0)
+    e = np.linspace(0, 40, 21)
+    check_case("rmu-mid-dd", d, None, cute.BIN_RMU, e, np.linspace(0, 1, 11), los=cute.LOS_MIDPOINT)
+    check_case("rmu-mid-dr", d, r, cute.BIN_RMU, e, np.linspace(0, 1, 11), los=cute.LOS_MIDPOINT)
+    check_case("sigmapi-dd", d, None, cute.BIN_SIGMAPI, e, e, los=cute.LOS_MIDPOINT)
+    check_case("sigmapi-dr", d, r, cute.BIN_SIGMAPI, e, e, los=cute.LOS_MIDPOINT)
+
+
+@pytest.mark.parametrize("centre", [(180.0, 0.0), (0.0, 10.0), (45.0, 89.0), (300.0, -88.5)])
+def test_theta_caps(centre):
+    """Equatorial cap, a cap straddling RA = 0 and caps around both poles."""
+    d, r = catalogs.config4(n_centres=60, per_blob=50, n_rand=9000, half_angle_deg=3.0,
+                            centre=centre)
+    e = np.deg2rad(np.geomspace(0.001, 2.0, 16))
+    check_case("theta-dd-%s" % (centre,), d, None, cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
+    check_case("theta-dr-%s" % (centre,), d, r, cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
+
+
+def test_theta_linear_bins_large_angles():
+    g = np.random.Generator(np.random.PCG64(7))
+    v = g.normal(size=(5000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    e = np.deg2rad(np.linspace(0, 30, 13))
+    check_case("theta-fullsky-lin", v, None, cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+def test_empty_and_single_point_catalogs():
+    e = np.linspace(0, 10, 6)
+    bn = cute.Binning(cute.BIN_MONO, e)
+    empty = np.zeros((0, 3))
+    one = np.array([[1.0, 2.0, 3.0]])
+    some = catalogs.uniform_box(500, 20.0, seed=3).stacked()
+    for prec in EXACT + [cute.PREC_FP32_ONLY]:
+        say("case empty prec", prec)
+        assert gpu_counts(empty, None, bn, prec, cute.GEOM_BOX_OPEN).sum() == 0
+        assert gpu_counts(one, None, bn, prec, cute.GEOM_BOX_OPEN).sum() == 0
+        assert gpu_counts(empty, some, bn, prec, cute.GEOM_BOX_OPEN).sum() == 0
+        assert gpu_counts(some, empty, bn, prec, cute.GEOM_BOX_OPEN).sum() == 0
+        got = gpu_counts(one, some, bn, prec, cute.GEOM_BOX_OPEN)
+        want = oracle.count_pairs(one, some, obin(cute.BIN_MONO, e)).reshape(-1)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_duplicates_and_zero_separation():
+    pts = np.repeat(np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 8.0]]), 70, axis=0)
+    check_case("dups-mono", pts, None, cute.BIN_MONO, [0.0, 1.0, 2.0, 4.0])
+    check_case("dups-rmu", pts, None, cute.BIN_RMU, [0.0, 1.0, 2.0, 4.0], [0.0, 0.5, 1.0])
+    check_case("dups-rmu-cross", pts, pts[::3], cute.BIN_RMU, [0.0, 1.0, 2.0, 4.0], [0.0, 0.5, 1.0])
+
+
+def test_dyadic_lattice_on_edges():
+    """Lattice points give many pairs exactly on r and mu edges; every FP64
+    operation is exact there, so FP32_EDGE must resolve each one like FP64."""
+    g = np.random.Generator(np.random.PCG64(9))
+    pts = g.integers(0, 24, size=(3000, 3)).astype(np.float64) * 0.5
+    check_case("lattice-mono", pts, None, cute.BIN_MONO, np.arange(0, 9) * 0.5)
+    check_case("lattice-rmu", pts, None, cute.BIN_RMU, np.arange(0, 9) * 0.5,
+               np.array([0.0, 0.25, 0.5, 0.75, 1.0]))
+    check_case("lattice-mono-periodic", pts, None, cute.BIN_MONO, np.arange(0, 9) * 0.5,
+               geom=cute.GEOM_BOX_PERIODIC, L=12.0)
+
+
+def test_periodic_pairs_across_faces():
+    L = 100.0
+    a = np.array([[0.0, 0.0, 0.0], [99.5, 0.25, 50.0], [50.0, 99.75, 0.5], [0.5, 0.5, 99.5]])
+    b = catalogs.uniform_box(3000, L, seed=5).stacked()
+    pts = np.concatenate([a, b])
+    check_case("faces", pts, None, cute.BIN_MONO, np.linspace(0, 20, 11),
+               geom=cute.GEOM_BOX_PERIODIC, L=L)
+
+
+# ---------------------------------------------------------------------------
+# Properties that hold at any size
+# ---------------------------------------------------------------------------
+def test_symmetry_and_fp32_only_bound():
+    d, r = catalogs.config2(n_centres=200, per_blob=50, n_rand=20000, box=400.0)
+    bn = cute.Binning(cute.BIN_RMU, np.linspace(0, 50, 11), np.linspace(0, 1, 21))
+    ga, gb = cute.build_grid(d, cute.GEOM_BOX_OPEN, r_max=50.0), cute.build_grid(r, cute.GEOM_BOX_OPEN, r_max=50.0)
+    say("case symmetry")
+    ab, st = cute.count_pairs(ga, gb, bn, cute.PREC_FP32_EDGE, with_stats=True)
+    ba = cute.count_pairs(gb, ga, bn, cute.PREC_FP32_EDGE)
+    np.testing.assert_array_equal(ab, ba)
+    ab64 = cute.count_pairs(ga, gb, bn, cute.PREC_FP64)
+    np.testing.assert_array_equal(ab, ab64)
+    only = cute.count_pairs(ga, gb, bn, cute.PREC_FP32_ONLY).astype(np.int64)
+    l1 = int(np.abs(only - ab.astype(np.int64)).sum())
+    assert l1 <= 2 * st["flips"]
+    assert st["retests"] >= st["flips"]
+    say("retest fraction %.2e flips %d l1 %d" % (st["retests"] / max(1, st["pair_evals"]),
+                                                 st["flips"], l1))
+
+
+# ---------------------------------------------------------------------------
+# Estimators and multipoles (host arithmetic in the library)
+# ---------------------------------------------------------------------------
+def test_estimators_match_exact_rationals():
+    g = np.random.Generator(np.random.PCG64(11))
+    nd, nr = 1_000_000, 2_000_000
+    rr = g.integers(1, 10 ** 12, size=(8, 5)).astype(np.uint64)
+    dd = (rr.astype(np.float64) * (nd * (nd - 1)) / (nr * (nr - 1)) * (1 + g.normal(0, 1e-4, rr.shape)))
+    dd = np.rint(dd).astype(np.uint64)
+    dr = (rr.astype(np.float64) * (2 * nd) / (nr - 1) * (1 + g.normal(0, 1e-4, rr.shape)))
+    dr = np.rint(dr).astype(np.uint64)
+    rr[0, 0] = 0
+    bn = cute.Binning(cute.BIN_RMU, np.linspace(0, 40, 9), np.linspace(0, 1, 6))
+    for e, ref in ((cute.EST_NATURAL, est.natural(dd, rr, nd, nr)),
+                   (cute.EST_LS, est.landy_szalay(dd, dr, rr, nd, nr))):
+        got = cute.xi_estimate(e, dd, dr, rr, nd, nr, bn)
+        assert math.isnan(got[0, 0]) and math.isnan(ref[0, 0])
+        m = ~np.isnan(ref)
+        rel = np.abs(got[m] - ref[m]) / np.maximum(np.abs(ref[m]), 1e-300)
+        assert rel.max() <= 1e-12, rel.max()
+    e = np.arange(31) * 5.0
+    ddb = g.integers(10, 10 ** 6, size=30).astype(np.uint64)
+    got = cute.xi_estimate(cute.EST_BOX, ddb, None, None, 20000, 0, cute.Binning(cute.BIN_MONO, e),
+                           box_size=1000.0)
+    ref = est.box(ddb, 20000, 1000.0, e)
+    assert np.max(np.abs((1 + got) - (1 + ref)) / (1 + ref)) <= 1e-13
+
+
+def test_multipoles_match_exact_rationals():
+    g = np.random.Generator(np.random.PCG64(12))
+    mu = np.linspace(0, 1, 51)
+    xi = g.normal(size=(40, 50))
+    bn = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, mu)
+    got = cute.xi_multipoles(xi, bn, (0, 2, 4))
+    ref = est.multipoles(xi, mu, [0, 2, 4])
+    for a, ell in enumerate((0, 2, 4)):
+        w = est.multipole_weights_abs(mu, ell)
+        scale = np.abs(xi) @ w
+        assert np.all(np.abs(got[a] - ref[a]) <= 1e-12 * scale + 1e-300)

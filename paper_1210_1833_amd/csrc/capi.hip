@@ -239,6 +239,8 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     a.n1 = n1;
     a.n2 = n2;
     a.nbins = nbins;
+    a.n1m1 = (float)(n1 - 1);
+    a.n2m1 = (float)(n2 > 0 ? n2 - 1 : 0);
     a.mu_top_closed = (bins->kind == CUTE_BIN_RMU && bins->edges2[n2] >= 1.0) ? 1 : 0;
 
     // ---- stencil radius ----------------------------------------------------
@@ -417,7 +419,8 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     // ---- LDS plan: waves per workgroup and histogram copies ------------------
     const size_t tables = 8 * (size_t)(n1 + 1) + 8 * (size_t)(n2 + 1) + 8 * (size_t)n1 +
                           8 * (size_t)std::max(n2, 1);
-    const size_t budget = 80 * 1024;
+    // about 40 KB per 4-wave workgroup keeps four workgroups (16 waves) per CU
+    const size_t budget = 40 * 1024;
     int W = 0, C = 0;
     for (int w : {4, 2, 1}) {
         const size_t fixed = tables + (size_t)w * 12 * kQCap;

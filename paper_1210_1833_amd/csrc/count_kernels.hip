@@ -40,7 +40,7 @@ typedef const __attribute__((address_space(4))) uint32_t* cu32p;
 
 __device__ __forceinline__ float4 load_u32x4f(const float4* p, uint32_t j) {
     const cfp f = (cfp)(const void*)p;
-    return make_float4(f[4 * j], f[4 * j + 1], f[4 * j + 2], 0.0f);
+    return make_float4(f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3]);
 }
 __device__ __forceinline__ P64 load_u64x3(const P64* p, uint32_t j) {
     const cdp f = (cdp)(const void*)p;
@@ -155,14 +155,13 @@ __device__ __forceinline__ int guess1(const CountArgs& P, float v) {
     } else {
         t = (EST == E_LOG) ? __builtin_amdgcn_logf(v) : __builtin_amdgcn_sqrtf(v);
     }
-    float f = fminf(fmaxf(fmaf(t, P.e1a, P.e1b), 0.0f), (float)(P.n1 - 1));
-    return (int)f;
+    return (int)__builtin_amdgcn_fmed3f(fmaf(t, P.e1a, P.e1b), 0.0f, P.n1m1);
 }
 
-__device__ __forceinline__ int guess_lin(float t, float a, float b, int n) {
-    // fmaxf returns the non-NaN operand, so a NaN estimate lands in bin 0
-    float f = fminf(fmaxf(fmaf(t, a, b), 0.0f), (float)(n - 1));
-    return (int)f;
+// clamp to [0, n-1] with one v_med3; a NaN estimate converts to bin 0 or is
+// clamped, so the index always stays in range
+__device__ __forceinline__ int guess_lin(float t, float a, float b, float nm1) {
+    return (int)__builtin_amdgcn_fmed3f(fmaf(t, a, b), 0.0f, nm1);
 }
 
 // Canonical classification of a queued pair from the sorted FP64 copies.
@@ -186,18 +185,18 @@ __device__ uint32_t classify_pair64(const CountArgs& P, const double* T1, const 
         float inv = ll > 0.0 ? (float)(1.0 / ll) : 0.0f;
         float pi2 = (float)(sl * sl) * inv;
         float sg2 = fmaxf(v - pi2, 0.0f);
-        k1 = guess_lin(__builtin_amdgcn_sqrtf(sg2), P.e1a, P.e1b, P.n1);
-        k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2);
+        k1 = guess_lin(__builtin_amdgcn_sqrtf(sg2), P.e1a, P.e1b, P.n1m1);
+        k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2m1);
     } else {
         k1 = guess1<MODE, EST>(P, v);
         if (MODE == M_RMU_Z) {
             float mu = d2 > 0.0 ? (float)(fabs(dz) / sqrt(d2)) : 0.0f;
-            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2);
+            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
         } else if (MODE == M_RMU_MID) {
             double sl = fma(dz, lz, fma(dy, ly, dx * lx));
             double ll = fma(lz, lz, fma(ly, ly, lx * lx));
             float mu = (d2 > 0.0 && ll > 0.0) ? (float)(fabs(sl) / sqrt(d2 * ll)) : 0.0f;
-            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2);
+            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
         }
     }
     return classify64<MODE>(P, T1, T2, dx, dy, dz, lx, ly, lz, k1, k2);
@@ -222,13 +221,13 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
                                           float lx, float ly, float lz, uint32_t* tent) {
     C32 c;
     float v = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    if (MODE == M_MONO || MODE == M_THETA) {
+    if (MODE == M_MONO | MODE == M_THETA) {
         int k = guess1<MODE, EST>(P, v);
         float2 b = B1[k];
-        c.in = (v >= b.x) && (v < b.y);
-        c.out = (v >= P.out_hi) || (v < P.out_lo);
+        c.in = (v >= b.x) & (v < b.y);
+        c.out = (v >= P.out_hi) | (v < P.out_lo);
         c.bin = (uint32_t)k;
-        if (WANT_TENT) *tent = (v >= P.bot32 && v < P.top32) ? (uint32_t)k : kNoBin;
+        if (WANT_TENT) *tent = (v >= P.bot32 & v < P.top32) ? (uint32_t)k : kNoBin;
         return c;
     }
     if (MODE == M_RMU_Z) {
@@ -236,33 +235,30 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
         float r = v * rinv;
         int k;
         if (EST == E_LOG) {
-            k = guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1);
+            k = guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1m1);
         } else {
-            k = guess_lin(r, P.e1a, P.e1b, P.n1);
+            k = guess_lin(r, P.e1a, P.e1b, P.n1m1);
         }
         float mu = fabsf(dz) * rinv;
-        int km = guess_lin(mu, P.e2a, P.e2b, P.n2);
+        int km = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
         float dz2 = dz * dz;
         float2 b = B1[k];
         float2 m = B2[km];
         float delta = fmaf(P.dA2, v, fmaf(P.dA1, r, P.dA0));
         float flo = fmaf(m.x, v, dz2);
         float fhi = fmaf(m.y, v, dz2);
-        bool rin = (v >= b.x) && (v < b.y);
-        bool min_ = (flo >= delta) && (fhi <= -delta);
-        c.in = rin && min_;
-        c.out = (v >= P.out_hi) || (v < P.out_lo);
-        if (P.d2_partial) {
-            float f0 = fmaf(P.nlo2_first, v, dz2);
-            float fn = fmaf(P.nhi2_last, v, dz2);
-            c.out = c.out || (f0 <= -delta) || (fn >= delta);
-        }
-        c.bin = (uint32_t)(k * P.n2 + km);
+        bool rin = (v >= b.x) & (v < b.y);
+        bool min_ = (flo >= delta) & (fhi <= -delta);
+        c.in = rin & min_;
+        // only r decides a clean "out"; a pair outside a partial mu range is
+        // re-tested instead (never the case for mu in [0, 1])
+        c.out = (v >= P.out_hi) | (v < P.out_lo);
+        c.bin = __umul24((uint32_t)k, (uint32_t)P.n2) + (uint32_t)km;
         if (WANT_TENT) {
-            bool rr = v >= P.bot32 && v < P.top32;
+            bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;
-            if (P.d2_partial) mm = (fmaf(P.nlo2_first, v, dz2) >= 0.0f) && (fmaf(P.nhi2_last, v, dz2) < 0.0f);
-            *tent = (rr && mm) ? c.bin : kNoBin;
+            if (P.d2_partial) mm = (fmaf(P.nlo2_first, v, dz2) >= 0.0f) & (fmaf(P.nhi2_last, v, dz2) < 0.0f);
+            *tent = (rr & mm) ? c.bin : kNoBin;
         }
         return c;
     }
@@ -271,13 +267,13 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
         float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
         float rinv = __builtin_amdgcn_rsqf(v);
         float r = v * rinv;
-        int k = (EST == E_LOG) ? guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1)
-                               : guess_lin(r, P.e1a, P.e1b, P.n1);
+        int k = (EST == E_LOG) ? guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1m1)
+                               : guess_lin(r, P.e1a, P.e1b, P.n1m1);
         float w = v * ll;
         float sl2 = sl * sl;
         float lnorm = __builtin_amdgcn_sqrtf(ll);
         float mu = fabsf(sl) * rinv * __builtin_amdgcn_rcpf(lnorm);
-        int km = guess_lin(mu, P.e2a, P.e2b, P.n2);
+        int km = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
         float2 b = B1[k];
         float2 m = B2[km];
         float delta = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, r, P.dA0)),
@@ -285,21 +281,16 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
                                 fmaf(P.dC2, v, P.dC0)));
         float flo = fmaf(m.x, w, sl2);
         float fhi = fmaf(m.y, w, sl2);
-        bool rin = (v >= b.x) && (v < b.y);
-        bool min_ = (flo >= delta) && (fhi <= -delta);
-        c.in = rin && min_;
-        c.out = (v >= P.out_hi) || (v < P.out_lo);
-        if (P.d2_partial) {
-            float f0 = fmaf(P.nlo2_first, w, sl2);
-            float fn = fmaf(P.nhi2_last, w, sl2);
-            c.out = c.out || (f0 <= -delta) || (fn >= delta);
-        }
-        c.bin = (uint32_t)(k * P.n2 + km);
+        bool rin = (v >= b.x) & (v < b.y);
+        bool min_ = (flo >= delta) & (fhi <= -delta);
+        c.in = rin & min_;
+        c.out = (v >= P.out_hi) | (v < P.out_lo);
+        c.bin = __umul24((uint32_t)k, (uint32_t)P.n2) + (uint32_t)km;
         if (WANT_TENT) {
-            bool rr = v >= P.bot32 && v < P.top32;
+            bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;
-            if (P.d2_partial) mm = (fmaf(P.nlo2_first, w, sl2) >= 0.0f) && (fmaf(P.nhi2_last, w, sl2) < 0.0f);
-            *tent = (rr && mm) ? c.bin : kNoBin;
+            if (P.d2_partial) mm = (fmaf(P.nlo2_first, w, sl2) >= 0.0f) & (fmaf(P.nhi2_last, w, sl2) < 0.0f);
+            *tent = (rr & mm) ? c.bin : kNoBin;
         }
         return c;
     }
@@ -311,8 +302,8 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
     float rll = __builtin_amdgcn_rcpf(ll);
     float sg = __builtin_amdgcn_sqrtf(fmaxf(c2 * rll, 0.0f));
     float pp = __builtin_amdgcn_sqrtf(sl2 * rll);
-    int ks = guess_lin(sg, P.e1a, P.e1b, P.n1);
-    int kp = guess_lin(pp, P.e2a, P.e2b, P.n2);
+    int ks = guess_lin(sg, P.e1a, P.e1b, P.n1m1);
+    int kp = guess_lin(pp, P.e2a, P.e2b, P.n2m1);
     float t = __builtin_amdgcn_sqrtf(v);
     float lnorm = __builtin_amdgcn_sqrtf(ll);
     float ds = fmaf(ll, fmaf(P.sA2, v, fmaf(P.sA1, t, P.sA0)),
@@ -323,16 +314,16 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
     float2 bp = B2[kp];
     float fslo = fmaf(bs.x, ll, c2), fshi = fmaf(bs.y, ll, c2);
     float fplo = fmaf(bp.x, ll, sl2), fphi = fmaf(bp.y, ll, sl2);
-    c.in = (fslo >= ds) && (fshi <= -ds) && (fplo >= dp) && (fphi <= -dp);
+    c.in = (fslo >= ds) & (fshi <= -ds) & (fplo >= dp) & (fphi <= -dp);
     // out of range: sigma >= sigma_max, pi >= pi_max, or below the first edges
     float fstop = fmaf(P.out_hi, ll, c2);       // out_hi holds -S2f[n1]
     float fptop = fmaf(P.nhi2_last, ll, sl2);   // -P2f[n2]
     float fsbot = fmaf(P.out_lo, ll, c2);       // out_lo holds -S2f[0] (or +BIG)
     float fpbot = fmaf(P.nlo2_first, ll, sl2);  // -P2f[0] (or +BIG)
-    c.out = (fstop >= ds) || (fptop >= dp) || (fsbot <= -ds) || (fpbot <= -dp);
-    c.bin = (uint32_t)(ks * P.n2 + kp);
+    c.out = (fstop >= ds) | (fptop >= dp) | (fsbot <= -ds) | (fpbot <= -dp);
+    c.bin = __umul24((uint32_t)ks, (uint32_t)P.n2) + (uint32_t)kp;
     if (WANT_TENT) {
-        bool ok = (fsbot >= 0.0f) && (fstop < 0.0f) && (fpbot >= 0.0f) && (fptop < 0.0f);
+        bool ok = (fsbot >= 0.0f) & (fstop < 0.0f) & (fpbot >= 0.0f) & (fptop < 0.0f);
         *tent = ok ? c.bin : kNoBin;
     }
     return c;
@@ -372,7 +363,7 @@ __device__ void drain_queue(const CountArgs& P, WaveState& W, const double* T1, 
             k = classify_pair64<MODE, EST>(P, T1, T2, p, q);
             if (k != kNoBin) hist_add(W.hist, k, P.copies, lane);
         }
-        const uint64_t fl = __ballot(act && k != t);
+        const uint64_t fl = __builtin_amdgcn_ballot_w64(act && k != t);
         W.flips += (uint64_t)__popcll(fl);
         W.retests += n;
         const uint32_t rest = W.tail - n;
@@ -406,47 +397,107 @@ __device__ void wave_flush(const CountArgs& P, WaveState& W, const double* T1, c
 // already moved into the neighbour grid's frame for this span. If masked,
 // only neighbours with index > the lane's home index count (autocorrelation
 // inside the home tile).
+// Queue the ambiguous pairs of one neighbour point for the FP64 re-test.
+template <int MODE, int EST>
+__device__ __forceinline__ void enqueue(const CountArgs& P, WaveState& W, const float2* B1,
+                                        const float2* B2, const double* T1, const double* T2,
+                                        int lane, bool amb, uint32_t hidx, uint32_t j, float hx,
+                                        float hy, float hz, float hlx, float hly, float hlz,
+                                        const float4& q) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
+    if (m == 0) return;
+    const float dx = hx - q.x, dy = hy - q.y, dz = hz - q.z;
+    float lx = 0.f, ly = 0.f, lz = 0.f;
+    if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
+        lx = hlx + q.x;
+        ly = hly + q.y;
+        lz = hlz + q.z;
+    }
+    uint32_t tent;
+    (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent);
+    const uint32_t pre =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (amb) {
+        const uint32_t pos = W.tail + pre;
+        W.qi[pos] = hidx;
+        W.qj[pos] = j;
+        W.qt[pos] = tent;
+    }
+    W.tail += (uint32_t)__popcll(m);
+    if (W.tail >= 64u) drain_queue<MODE, EST>(P, W, T1, T2, lane, false);
+}
+
+// U neighbour points per step: their scalar loads are issued together and
+// the U classifications form one straight-line block that the compiler can
+// interleave; the LDS increments and the (rare) re-test queueing follow.
+template <int MODE, int PREC, int EST, bool MASKED, uint32_t U>
+__device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const float2* B1,
+                                       const float2* B2, const double* T1, const double* T2,
+                                       int lane, bool valid, uint32_t hidx, float hx, float hy,
+                                       float hz, float hlx, float hly, float hlz, uint32_t j) {
+    float4 q[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) q[u] = load_u32x4f(P.B.p32, j + u);
+    uint32_t bin[U];
+    bool cnt[U], amb[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        const bool act = valid & (!MASKED | (j + u > hidx));
+        const float dx = hx - q[u].x, dy = hy - q[u].y, dz = hz - q[u].z;
+        float lx = 0.f, ly = 0.f, lz = 0.f;
+        if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
+            lx = hlx + q[u].x;
+            ly = hly + q[u].y;
+            lz = hlz + q[u].z;
+        }
+        if (PREC == P_FP32O) {
+            uint32_t tent;
+            (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent);
+            cnt[u] = act && tent != kNoBin;
+            bin[u] = tent;
+            amb[u] = false;
+        } else {
+            const C32 c = classify32<MODE, EST, false>(P, B1, B2, dx, dy, dz, lx, ly, lz, nullptr);
+            cnt[u] = act & c.in;
+            amb[u] = act & !(c.in | c.out);
+            bin[u] = c.bin;
+        }
+    }
+    // the wave-wide "any ambiguous" vote is taken before the increments so
+    // that the ambiguity masks are consumed while they are still compare results
+    uint64_t any_amb = 0;
+    if (PREC == P_FP32E) {
+        bool any = false;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) any = any | amb[u];
+        any_amb = __builtin_amdgcn_ballot_w64(any);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++)
+        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane);
+    if (PREC == P_FP32E) {
+        if (any_amb) {
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++)
+                enqueue<MODE, EST>(P, W, B1, B2, T1, T2, lane, amb[u], hidx, j + u, hx, hy, hz,
+                                   hlx, hly, hlz, q[u]);
+        }
+    }
+}
+
 template <int MODE, int PREC, int EST, bool MASKED>
 __device__ void run_span32(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
                            const double* T1, const double* T2, int lane, bool valid,
                            uint32_t hidx, float hx, float hy, float hz, float hlx, float hly,
                            float hlz, uint32_t j0, uint32_t j1) {
-    for (uint32_t j = j0; j < j1; j++) {
-        const float4 q = load_u32x4f(P.B.p32, j);
-        bool act = valid && (!MASKED || j > hidx);
-        float dx = hx - q.x, dy = hy - q.y, dz = hz - q.z;
-        float lx = 0.f, ly = 0.f, lz = 0.f;
-        if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-            lx = hlx + q.x;
-            ly = hly + q.y;
-            lz = hlz + q.z;
-        }
-        if (PREC == P_FP32O) {
-            uint32_t tent;
-            (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent);
-            if (act && tent != kNoBin) hist_add(W.hist, tent, P.copies, lane);
-        } else {
-            C32 c = classify32<MODE, EST, false>(P, B1, B2, dx, dy, dz, lx, ly, lz, nullptr);
-            const bool cnt = act && c.in;
-            const bool amb = act && !(c.in || c.out);
-            const uint64_t m = __ballot(amb);
-            if (cnt) hist_add(W.hist, c.bin, P.copies, lane);
-            if (m) {
-                uint32_t tent;
-                (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent);
-                uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (amb) {
-                    uint32_t pos = W.tail + pre;
-                    W.qi[pos] = hidx;
-                    W.qj[pos] = j;
-                    W.qt[pos] = tent;
-                }
-                W.tail += (uint32_t)__popcll(m);
-                if (W.tail >= 64u) drain_queue<MODE, EST>(P, W, T1, T2, lane, false);
-            }
-        }
-    }
+    constexpr uint32_t U = 4;
+    uint32_t j = j0;
+    for (; j + U <= j1; j += U)
+        step32<MODE, PREC, EST, MASKED, U>(P, W, B1, B2, T1, T2, lane, valid, hidx, hx, hy, hz,
+                                           hlx, hly, hlz, j);
+    for (; j < j1; j++)
+        step32<MODE, PREC, EST, MASKED, 1>(P, W, B1, B2, T1, T2, lane, valid, hidx, hx, hy, hz,
+                                           hlx, hly, hlz, j);
 }
 
 template <int MODE, int EST, bool MASKED>
@@ -479,21 +530,21 @@ __device__ void run_span64(const CountArgs& P, WaveState& W, const double* T1, c
         } else if (MODE == M_RMU_Z) {
             k1 = guess1<M_MONO, EST>(P, v);
             float rinv = __builtin_amdgcn_rsqf(v);
-            k2 = guess_lin(fabsf((float)dz) * rinv, P.e2a, P.e2b, P.n2);
+            k2 = guess_lin(fabsf((float)dz) * rinv, P.e2a, P.e2b, P.n2m1);
         } else if (MODE == M_RMU_MID) {
             k1 = guess1<M_MONO, EST>(P, v);
             float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
             float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
             float mu = fabsf(sl) * __builtin_amdgcn_rsqf(v * ll);
-            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2);
+            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
         } else {
             float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
             float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
             float rll = __builtin_amdgcn_rcpf(ll);
             float pi2 = sl * sl * rll;
             float sg2 = fmaxf(v - pi2, 0.0f);
-            k1 = guess_lin(__builtin_amdgcn_sqrtf(sg2), P.e1a, P.e1b, P.n1);
-            k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2);
+            k1 = guess_lin(__builtin_amdgcn_sqrtf(sg2), P.e1a, P.e1b, P.n1m1);
+            k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2m1);
         }
         uint32_t k = classify64<MODE>(P, T1, T2, dx, dy, dz, lx, ly, lz, k1, k2);
         if (act && k != kNoBin) hist_add(W.hist, k, P.copies, lane);

@@ -58,6 +58,7 @@ struct CountArgs {
     double th_s;                    // SPHERE: angular stencil radius (radians)
     double sin_th_s;                // SPHERE: sin(th_s)
     int n1, n2, nbins;
+    float n1m1, n2m1;               // n1 - 1 and n2 - 1 as floats (estimate clamps)
     int copies;                     // LDS histogram copies per wave (power of two)
     int hist_words;                 // nbins * copies
     uint32_t flush_budget;          // per-wave candidate pairs between flushes

@@ -66,6 +66,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cell-size", type=float, default=0.0,
+                    help="cell side of the grid (0 = the library's choice)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -90,7 +94,7 @@ def main():
     torch.cuda.synchronize()
 
     def step(prec):
-        g = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0)
+        g = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0, cell_size=args.cell_size)
         _, st = cute.count_pairs(g, None, bn, prec, out=counts, with_stats=True)
         g.close()
         return st
@@ -105,6 +109,14 @@ def main():
         dt = time.perf_counter() - t0
         return dt, sts
 
+    if args.copy_probe_mib:
+        # a plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy probe of %d MiB done" % args.copy_probe_mib)
+        del src, dst
     log("bench: r-mu DD, n=%d, FP32_EDGE %d steps" % (n, args.steps))
     dt32, st32 = run(cute.PREC_FP32_EDGE, args.steps, args.warmup)
     c32 = counts.cpu().numpy().astype(np.uint64)
@@ -152,10 +164,12 @@ def main():
             "n_points": n,
             "step": "cute_build_grid + cute_count_pairs (auto), inputs resident in HBM",
             "precision": "FP32_EDGE",
+            "cell_size": args.cell_size or "auto",
         },
         "bit_exact": exact,
         "checked_against": "oracle golden counts" if oracle_checked else "GPU FP64 path",
         "pair_evals_per_step": int(evals),
+        "tiles_per_step": int(st32[-1]["tiles"]),
         "pairs_in_range_per_step": in_range,
         "retests_per_step": int(st32[-1]["retests"]),
         "fp32_only_miscounts_per_step": int(st32[-1]["flips"]),

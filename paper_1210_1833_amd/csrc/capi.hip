@@ -55,6 +55,7 @@ constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 constexpr float kBig = 1e30f;
 constexpr int kQCap = 128;                        // must match the kernels
+constexpr int kSpanCap = 192;                     // must match the kernels
 
 float up32(double x) {
     float f = (float)x;
@@ -275,7 +276,10 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     max_w = std::min(max_w, 65535);
 
     // ---- FP32 error model --------------------------------------------------
-    // ec bounds |FP32 coordinate difference - exact difference| per component.
+    // ec bounds |FP32 coordinate difference - exact difference| per component:
+    // rounding of both FP32 copies (u X_A + u X_B), the neighbour moved into
+    // the home frame, q - off with off = FP32(cA - cB) or a periodic image
+    // shift (u |off| + u (X_B + |off|)), and the final subtraction (u R).
     double offmax = 0.0;
     if (periodic) {
         offmax = A.L;
@@ -288,7 +292,7 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     a.offy = is_auto || periodic || sphere ? 0.f : (float)(A.cy - B.cy);
     a.offz = is_auto || periodic || sphere ? 0.f : (float)(A.cz - B.cz);
     const double Re = rmax * 1.01 + 1e-30;
-    const double extra = offmax > 0.0 ? kU32 * offmax + kU32 * (A.ext + offmax) : 0.0;
+    const double extra = offmax > 0.0 ? kU32 * offmax + kU32 * (B.ext + offmax) : 0.0;
     const double ec = 1.0001 * (kU32 * A.ext + kU32 * B.ext + extra + kU32 * Re);
     const double ec64 = 2.0 * kU64 * (A.rawmax + B.rawmax + (periodic ? A.L : 0.0)) * 1.0001;
     const double s3 = std::sqrt(3.0);
@@ -369,18 +373,22 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
         // |F - exact| <= 2 sqrt(2) ec r + 3 ec^2 + 8.1 u S, plus the FP64 terms;
         // r is bounded by the FP32 estimate r (1 + 5u) + sqrt(3) ec
         const double k1 = 2 * std::sqrt(2.0) * ec + (2 + 2 * s3) * ec64;
-        a.dA1 = (float)(1.5 * k1 * (1 + 8 * kU32));
+        // the kernel uses delta = dA0 + dA1 r with the v term folded in:
+        // A2 v <= A2 Re r for every pair whose mu decision counts (r < Re)
+        const double a2 = 1.5 * (8.1 * kU32 + 16 * kU64) * 1.0001;
+        a.dA1 = (float)((1.5 * k1 * (1 + 8 * kU32) + a2 * Re) * 1.0001);
         a.dA0 = (float)(1.5 * (k1 * s3 * ec + 3 * ec * ec + 4 * ec64 * ec64) * 1.0001);
-        a.dA2 = (float)(1.5 * (8.1 * kU32 + 16 * kU64) * 1.0001);
+        a.dA2 = 0.0f;
     } else if (mid) {
         // midpoint line of sight: perturbations of s = p - q (per component
         // <= ec) and l = p + q (per component <= el) move the ratio predicates
         // by first-order terms ~ r |s-error| ll and r^2 |l| |l-error|
-        const double el =
-            1.0001 * kU32 *
-            (A.ext + B.ext + extra + 2 * std::max({std::fabs(B.cx), std::fabs(B.cy), std::fabs(B.cz)}) +
-             (A.ext + offmax + 2 * std::max({std::fabs(B.cx), std::fabs(B.cy), std::fabs(B.cz)})) +
-             (A.lmax + B.lmax));
+        // l = h + ((q - off) + FP32(2 cA)): the roundings of both copies, of the
+        // frame shift, of 2 cA, of the two additions (|l| <= max|p| + max|q|)
+        const double ca = std::max({std::fabs(A.cx), std::fabs(A.cy), std::fabs(A.cz)});
+        const double el = 1.0001 * kU32 *
+                          (A.ext + B.ext + extra + 2 * ca + (B.ext + offmax + 2 * ca) +
+                           (A.lmax + B.lmax));
         const double es = s3 * ec, esl = s3 * el;
         const double es64 = s3 * ec64, el64 = s3 * 2.0 * kU64 * (A.lmax + B.lmax);
         auto fill = [&](double c_lin, double c_round, double kmax2, float* A0, float* A1, float* A2,
@@ -411,43 +419,45 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
         } else {
             fill(4.0, 17.5, 1.0, &a.dA0, &a.dA1, &a.dA2, &a.dB0, &a.dB1, &a.dB2, &a.dC2, &a.dC0);
         }
-        a.lcx = (float)(2.0 * B.cx);
-        a.lcy = (float)(2.0 * B.cy);
-        a.lcz = (float)(2.0 * B.cz);
+        a.lcx = (float)(2.0 * A.cx);
+        a.lcy = (float)(2.0 * A.cy);
+        a.lcz = (float)(2.0 * A.cz);
     }
 
-    // ---- LDS plan: waves per workgroup and histogram copies ------------------
+    // ---- LDS plan: one shared 64-bit histogram per 4-wave workgroup --------
+    // About 40 KB per workgroup keeps four workgroups (16 waves) on a CU; the
+    // copies of the histogram are cut to fit, then the budget is relaxed for
+    // very large histograms (fewer workgroups per CU).
     const size_t tables = 8 * (size_t)(n1 + 1) + 8 * (size_t)(n2 + 1) + 8 * (size_t)n1 +
                           8 * (size_t)std::max(n2, 1);
-    // about 40 KB per 4-wave workgroup keeps four workgroups (16 waves) per CU
-    const size_t budget = 40 * 1024;
-    int W = 0, C = 0;
-    for (int w : {4, 2, 1}) {
-        const size_t fixed = tables + (size_t)w * 12 * kQCap;
-        if (fixed >= budget) continue;
-        size_t cmax = (budget - fixed) / ((size_t)w * 4 * nbins);
-        if (cmax < 1) continue;
-        int c = 1;
-        while (c * 2 <= (int)std::min<size_t>(cmax, 32)) c *= 2;
-        W = w;
-        C = c;
+    const int W = 4;
+    const size_t per_wave = 12 * (size_t)kQCap + 16 + 12 * (size_t)kSpanCap;
+    const size_t fixed = tables + (size_t)W * per_wave;
+    int C = 0;
+    for (size_t budget : {(size_t)40 * 1024, (size_t)80 * 1024, (size_t)160 * 1024}) {
+        if (fixed + 8 * (size_t)nbins > budget) continue;
+        size_t cmax = (budget - fixed) / (8 * (size_t)nbins);
+        C = 1;
+        while (C * 2 <= (int)std::min<size_t>(cmax, 32)) C *= 2;
         break;
     }
-    if (W == 0) return fail(CUTE_E_UNSUPPORTED, "histogram does not fit in LDS");
+    if (C == 0) return fail(CUTE_E_UNSUPPORTED, "histogram does not fit in LDS");
     a.copies = C;
     a.hist_words = nbins * C;
-    const size_t lds = tables + (size_t)W * ((size_t)4 * a.hist_words + 12 * kQCap);
+    const size_t lds = fixed + 8 * (size_t)a.hist_words;
 
     // ---- device buffers ----------------------------------------------------
     TempList tmp(hs);
     double *dT1, *dT2;
     float2 *dB1, *dB2;
     unsigned long long* work;  // counts[nbins], stats[4], head
+    CountArgs* dargs;
     if ((s = tmp.alloc(&dT1, pl.T1.size())) != CUTE_OK) return s;
     if ((s = tmp.alloc(&dT2, pl.T2.size())) != CUTE_OK) return s;
     if ((s = tmp.alloc(&dB1, pl.band1.size())) != CUTE_OK) return s;
     if ((s = tmp.alloc(&dB2, pl.band2.size())) != CUTE_OK) return s;
     if ((s = tmp.alloc(&work, (size_t)nbins + 5)) != CUTE_OK) return s;
+    if ((s = tmp.alloc(&dargs, 1)) != CUTE_OK) return s;
     CUTE_HIP(hipMemcpyAsync(dT1, pl.T1.data(), pl.T1.size() * 8, hipMemcpyHostToDevice, hs));
     CUTE_HIP(hipMemcpyAsync(dT2, pl.T2.data(), pl.T2.size() * 8, hipMemcpyHostToDevice, hs));
     CUTE_HIP(hipMemcpyAsync(dB1, pl.band1.data(), pl.band1.size() * 8, hipMemcpyHostToDevice, hs));
@@ -468,6 +478,8 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     }
     a.tiles = tiles;
     a.ntiles = ntiles;
+    a.self = dargs;
+    CUTE_HIP(hipMemcpyAsync(dargs, &a, sizeof(a), hipMemcpyHostToDevice, hs));
 
     double ms = 0.0;
     int grid = 0;

@@ -30,7 +30,8 @@ namespace {
 constexpr int kQCap = 128;             // retest queue entries per wave
 constexpr uint32_t kNoBin = 0xffffffffu;
 constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr uint32_t kChunk = 1u << 20;  // neighbour points per budget check
+constexpr uint32_t kTileMax = 64;      // home points per tile
+constexpr uint32_t kSpanCap = 192;     // neighbour spans buffered per wave
 
 // Read-only device memory seen through the constant address space: loads at
 // wave-uniform addresses become scalar (s_load) loads into SGPRs.
@@ -218,7 +219,8 @@ struct C32 {
 template <int MODE, int EST, bool WANT_TENT>
 __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
                                           const float2* B2, float dx, float dy, float dz,
-                                          float lx, float ly, float lz, uint32_t* tent) {
+                                          float lx, float ly, float lz, uint32_t* tent,
+                                          float dA0v) {
     C32 c;
     float v = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     if (MODE == M_MONO | MODE == M_THETA) {
@@ -244,7 +246,9 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
         float dz2 = dz * dz;
         float2 b = B1[k];
         float2 m = B2[km];
-        float delta = fmaf(P.dA2, v, fmaf(P.dA1, r, P.dA0));
+        // the v term of the band is folded into the r term on the host
+        // (v <= r_max r wherever the mu decision matters)
+        float delta = fmaf(P.dA1, r, dA0v);
         float flo = fmaf(m.x, v, dz2);
         float fhi = fmaf(m.y, v, dz2);
         bool rin = (v >= b.x) & (v < b.y);
@@ -332,139 +336,167 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
 // ---------------------------------------------------------------------------
 // Per-wave working state.
 // ---------------------------------------------------------------------------
-struct WaveState {
-    uint32_t* hist;      // hist_words words
-    uint32_t* qi;        // queue: home index
-    uint32_t* qj;        // queue: neighbour index
-    uint32_t* qt;        // queue: FP32 decision
-    uint32_t tail;       // queued entries (wave-uniform)
-    uint64_t since_flush;
-    uint64_t evals, retests, flips, tiles;
-};
+// Periodic image of a neighbour point: (kx+1) | (ky+1) << 2 | (kz+1) << 4,
+// k in {-1, 0, 1}; the image lies at q + k L in the home point's frame.
+constexpr uint32_t kNoShift = 0x15u;
 
-// copies is a power of two: word = (bin << log2(copies)) | (lane & (copies - 1))
-__device__ __forceinline__ void hist_add(uint32_t* hist, uint32_t bin, int copies, int lane) {
-    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
-    atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], 1u);
+__device__ __forceinline__ float shift32(uint32_t code, int axis, float Lf) {
+    return (float)((int)((code >> (2 * axis)) & 3u) - 1) * Lf;
+}
+__device__ __forceinline__ double shift64(uint32_t code, int axis, double L) {
+    return (double)((int)((code >> (2 * axis)) & 3u) - 1) * L;
 }
 
+// Per-wave state. The queue, the histogram and the re-test statistics live
+// in LDS; the rare paths below are real (non-inlined) calls that take the
+// queue length by value and return it, so the hot loop keeps few registers.
+struct WaveState {
+    unsigned long long* hist;  // the workgroup's shared 64-bit histogram (hist_words)
+    uint32_t* qi;        // re-test queue: home index
+    uint32_t* qj;        // re-test queue: neighbour index
+    uint32_t* qc;        // re-test queue: neighbour image code
+    unsigned long long* rstat;  // [0] retests, [1] flips (LDS)
+    uint32_t tail;       // queued entries (wave-uniform)
+    uint64_t evals, tiles;
+};
+
+// The workgroup's histogram: 64-bit LDS counters (no overflow, so no
+// flushing before the end of the kernel), several interleaved copies so that
+// lanes hitting the same bin use different banks. copies is a power of two:
+// word = (bin << log2(copies)) | (lane & (copies - 1)).
+__device__ __forceinline__ void hist_add(unsigned long long* hist, uint32_t bin, int copies,
+                                         int lane) {
+    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
+    atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], 1ull);
+}
+
+// The same increment with the lane's copy folded into its base pointer.
+__device__ __forceinline__ void hist_add_lane(unsigned long long* lhist, uint32_t bin, uint32_t lc) {
+    atomicAdd(&lhist[bin << lc], 1ull);
+}
+
+// Re-test up to 64 queued pairs per pass, one per lane, through the canonical
+// FP64 predicates; count the pairs whose FP32-only decision differs (flips).
+// Returns the new queue length.
 template <int MODE, int EST>
-__device__ void drain_queue(const CountArgs& P, WaveState& W, const double* T1, const double* T2,
-                            int lane, bool all) {
-    while (W.tail >= 64u || (all && W.tail > 0u)) {
-        const uint32_t n = W.tail < 64u ? W.tail : 64u;
+__device__ __attribute__((noinline)) uint32_t drain_queue(
+    const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
+    unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
+    const double* T2, int lane, uint32_t tail, bool all) {
+    const CountArgs& P = *Pg;
+    tail = uni(tail);
+    while (tail >= 64u || (all && tail > 0u)) {
+        const uint32_t n = tail < 64u ? tail : 64u;
         const bool act = (uint32_t)lane < n;
         uint32_t k = kNoBin, t = kNoBin;
         if (act) {
-            const uint32_t i = W.qi[lane], j = W.qj[lane];
-            t = W.qt[lane];
+            const uint32_t i = qi[lane], j = qj[lane], code = qc[lane];
             const P64 p = P.A.p64[i];
             const P64 q = P.B.p64[j];
             k = classify_pair64<MODE, EST>(P, T1, T2, p, q);
-            if (k != kNoBin) hist_add(W.hist, k, P.copies, lane);
+            if (k != kNoBin) hist_add(hist, k, P.copies, lane);
+            // the FP32-only decision of the same pair, as the main loop made it
+            const float4 a = P.A.p32[i];
+            const float4 b = P.B.p32[j];
+            const float Lf = (float)P.L;
+            const float qx = b.x - (P.offx - shift32(code, 0, Lf));
+            const float qy = b.y - (P.offy - shift32(code, 1, Lf));
+            const float qz = b.z - (P.offz - shift32(code, 2, Lf));
+            (void)classify32<MODE, EST, true>(P, B1, B2, a.x - qx, a.y - qy, a.z - qz,
+                                              a.x + (qx + P.lcx), a.y + (qy + P.lcy),
+                                              a.z + (qz + P.lcz), &t, P.dA0);
         }
         const uint64_t fl = __builtin_amdgcn_ballot_w64(act && k != t);
-        W.flips += (uint64_t)__popcll(fl);
-        W.retests += n;
-        const uint32_t rest = W.tail - n;
+        if (lane == 0) {
+            rstat[0] += n;
+            rstat[1] += (unsigned long long)__popcll(fl);
+        }
+        const uint32_t rest = tail - n;
         if ((uint32_t)lane < rest) {
-            const uint32_t a = W.qi[n + lane], b = W.qj[n + lane], c = W.qt[n + lane];
-            W.qi[lane] = a;
-            W.qj[lane] = b;
-            W.qt[lane] = c;
+            const uint32_t a = qi[n + lane], b = qj[n + lane], c = qc[n + lane];
+            qi[lane] = a;
+            qj[lane] = b;
+            qc[lane] = c;
         }
-        W.tail = rest;
+        tail = rest;
     }
+    return tail;
 }
 
-template <int MODE, int EST>
-__device__ void wave_flush(const CountArgs& P, WaveState& W, const double* T1, const double* T2,
-                           int lane) {
-    drain_queue<MODE, EST>(P, W, T1, T2, lane, true);
-    for (int b = lane; b < P.nbins; b += 64) {
-        uint64_t s = 0;
-        for (int c = 0; c < P.copies; c++) {
-            uint32_t* w = &W.hist[b * P.copies + c];
-            s += *w;
-            *w = 0u;
+// Queue the lanes set in m[u] (pair: home h + u, this lane's neighbour).
+template <int MODE, int EST, uint32_t U>
+__device__ __attribute__((noinline)) uint32_t enqueue(
+    const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
+    unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
+    const double* T2, int lane, uint32_t tail, uint32_t h, uint32_t lj, uint32_t lcode,
+    uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3) {
+    tail = uni(tail);
+    for (uint32_t u = 0; u < U; u++) {
+        const uint64_t m = u == 0 ? m0 : (u == 1 ? m1 : (u == 2 ? m2 : m3));
+        if (m == 0) continue;
+        const uint32_t pre =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if ((m >> lane) & 1ull) {
+            const uint32_t pos = tail + pre;
+            qi[pos] = h + u;
+            qj[pos] = lj;
+            qc[pos] = lcode;
         }
-        if (s) atomicAdd(&P.counts[b], (unsigned long long)s);
+        tail += (uint32_t)__popcll(m);
+        if (tail >= 64u)
+            tail = drain_queue<MODE, EST>(Pg, hist, qi, qj, qc, rstat, B1, B2, T1, T2, lane, tail,
+                                          false);
     }
-    W.since_flush = 0;
+    return tail;
 }
 
-// One span of neighbour points [j0, j1). The home point (hx, hy, hz) is
-// already moved into the neighbour grid's frame for this span. If masked,
-// only neighbours with index > the lane's home index count (autocorrelation
-// inside the home tile).
-// Queue the ambiguous pairs of one neighbour point for the FP64 re-test.
-template <int MODE, int EST>
-__device__ __forceinline__ void enqueue(const CountArgs& P, WaveState& W, const float2* B1,
-                                        const float2* B2, const double* T1, const double* T2,
-                                        int lane, bool amb, uint32_t hidx, uint32_t j, float hx,
-                                        float hy, float hz, float hlx, float hly, float hlz,
-                                        const float4& q) {
-    const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
-    if (m == 0) return;
-    const float dx = hx - q.x, dy = hy - q.y, dz = hz - q.z;
-    float lx = 0.f, ly = 0.f, lz = 0.f;
-    if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-        lx = hlx + q.x;
-        ly = hly + q.y;
-        lz = hlz + q.z;
-    }
-    uint32_t tent;
-    (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent);
-    const uint32_t pre =
-        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    if (amb) {
-        const uint32_t pos = W.tail + pre;
-        W.qi[pos] = hidx;
-        W.qj[pos] = j;
-        W.qt[pos] = tent;
-    }
-    W.tail += (uint32_t)__popcll(m);
-    if (W.tail >= 64u) drain_queue<MODE, EST>(P, W, T1, T2, lane, false);
-}
-
-// U neighbour points per step: their scalar loads are issued together and
-// the U classifications form one straight-line block that the compiler can
-// interleave; the LDS increments and the (rare) re-test queueing follow.
+// ---------------------------------------------------------------------------
+// The hot loop. A chunk holds up to 64 neighbour points, one per lane, in
+// VGPRs; the home points of the tile are wave-uniform and arrive through
+// scalar loads, U at a time, so that U independent pair evaluations per lane
+// interleave. Every lane evaluates the pair (home h, its neighbour).
+// ---------------------------------------------------------------------------
 template <int MODE, int PREC, int EST, bool MASKED, uint32_t U>
 __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const float2* B1,
                                        const float2* B2, const double* T1, const double* T2,
-                                       int lane, bool valid, uint32_t hidx, float hx, float hy,
-                                       float hz, float hlx, float hly, float hlz, uint32_t j) {
-    float4 q[U];
+                                       int lane, bool lvalid, bool lmask, uint32_t lj,
+                                       uint32_t lcode, float qx, float qy, float qz, float qlx,
+                                       float qly, float qlz, float dA0v, uint32_t h) {
+    float hx[U], hy[U], hz[U];
 #pragma unroll
-    for (uint32_t u = 0; u < U; u++) q[u] = load_u32x4f(P.B.p32, j + u);
+    for (uint32_t u = 0; u < U; u++) {
+        const float4 p = load_u32x4f(P.A.p32, h + u);
+        hx[u] = p.x;
+        hy[u] = p.y;
+        hz[u] = p.z;
+    }
     uint32_t bin[U];
     bool cnt[U], amb[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
-        const bool act = valid & (!MASKED | (j + u > hidx));
-        const float dx = hx - q[u].x, dy = hy - q[u].y, dz = hz - q[u].z;
+        const bool act = lvalid & (!MASKED | !lmask | (lj > h + u));
+        const float dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
         float lx = 0.f, ly = 0.f, lz = 0.f;
         if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-            lx = hlx + q[u].x;
-            ly = hly + q[u].y;
-            lz = hlz + q[u].z;
+            lx = hx[u] + qlx;
+            ly = hy[u] + qly;
+            lz = hz[u] + qlz;
         }
         if (PREC == P_FP32O) {
             uint32_t tent;
-            (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent);
-            cnt[u] = act && tent != kNoBin;
+            (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent, dA0v);
+            cnt[u] = act & (tent != kNoBin);
             bin[u] = tent;
             amb[u] = false;
         } else {
-            const C32 c = classify32<MODE, EST, false>(P, B1, B2, dx, dy, dz, lx, ly, lz, nullptr);
+            const C32 c =
+                classify32<MODE, EST, false>(P, B1, B2, dx, dy, dz, lx, ly, lz, nullptr, dA0v);
             cnt[u] = act & c.in;
             amb[u] = act & !(c.in | c.out);
             bin[u] = c.bin;
         }
     }
-    // the wave-wide "any ambiguous" vote is taken before the increments so
-    // that the ambiguity masks are consumed while they are still compare results
+    // one vote for the whole step; the per-pair votes only on the rare path
     uint64_t any_amb = 0;
     if (PREC == P_FP32E) {
         bool any = false;
@@ -472,136 +504,188 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const f
         for (uint32_t u = 0; u < U; u++) any = any | amb[u];
         any_amb = __builtin_amdgcn_ballot_w64(any);
     }
+    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)P.copies);
+    unsigned long long* lhist = W.hist + (lane & (P.copies - 1));
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane);
-    if (PREC == P_FP32E) {
-        if (any_amb) {
+        if (cnt[u]) hist_add_lane(lhist, bin[u], lc);
+    if (PREC == P_FP32E && any_amb) {
+        uint64_t m[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (uint32_t u = 0; u < U; u++)
-                enqueue<MODE, EST>(P, W, B1, B2, T1, T2, lane, amb[u], hidx, j + u, hx, hy, hz,
-                                   hlx, hly, hlz, q[u]);
-        }
+        for (uint32_t u = 0; u < U; u++) m[u] = __builtin_amdgcn_ballot_w64(amb[u]);
+        W.tail = enqueue<MODE, EST, U>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,
+                                       W.tail, h, lj, lcode, m[0], m[1], m[2], m[3]);
     }
 }
 
-template <int MODE, int PREC, int EST, bool MASKED>
-__device__ void run_span32(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
-                           const double* T1, const double* T2, int lane, bool valid,
-                           uint32_t hidx, float hx, float hy, float hz, float hlx, float hly,
-                           float hlz, uint32_t j0, uint32_t j1) {
-    constexpr uint32_t U = 4;
-    uint32_t j = j0;
-    for (; j + U <= j1; j += U)
-        step32<MODE, PREC, EST, MASKED, U>(P, W, B1, B2, T1, T2, lane, valid, hidx, hx, hy, hz,
-                                           hlx, hly, hlz, j);
-    for (; j < j1; j++)
-        step32<MODE, PREC, EST, MASKED, 1>(P, W, B1, B2, T1, T2, lane, valid, hidx, hx, hy, hz,
-                                           hlx, hly, hlz, j);
-}
-
-template <int MODE, int EST, bool MASKED>
-__device__ void run_span64(const CountArgs& P, WaveState& W, const double* T1, const double* T2,
-                           int lane, bool valid, uint32_t hidx, double hx, double hy, double hz,
-                           double sx, double sy, double sz, uint32_t j0, uint32_t j1) {
-    const bool shifted = (sx != 0.0) || (sy != 0.0) || (sz != 0.0);
-    for (uint32_t j = j0; j < j1; j++) {
-        const P64 q = load_u64x3(P.B.p64, j);
-        bool act = valid && (!MASKED || j > hidx);
-        double dx = hx - q.x, dy = hy - q.y, dz = hz - q.z;
-        if (shifted) {
-            // the span's periodic image: the same result as the minimum-image
-            // wrap for every pair the stencil can pair up (see host notes)
+template <int MODE, int EST, bool MASKED, bool SHIFTED, uint32_t U>
+__device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const double* T1,
+                                       const double* T2, int lane, bool lvalid, bool lmask,
+                                       uint32_t lj, double qx, double qy, double qz, double sx, double sy,
+                                       double sz, uint32_t h) {
+    double hx[U], hy[U], hz[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        const P64 p = load_u64x3(P.A.p64, h + u);
+        hx[u] = p.x;
+        hy[u] = p.y;
+        hz[u] = p.z;
+    }
+    uint32_t bin[U];
+    bool cnt[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        const bool act = lvalid & (!MASKED | !lmask | (lj > h + u));
+        double dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
+        if (SHIFTED) {
+            // the neighbour's periodic image: equal to the minimum-image wrap
+            // for every pair the stencil can form
             dx = dx - sx;
             dy = dy - sy;
             dz = dz - sz;
         }
         double lx = 0.0, ly = 0.0, lz = 0.0;
         if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-            lx = hx + q.x;
-            ly = hy + q.y;
-            lz = hz + q.z;
+            lx = hx[u] + qx;
+            ly = hy[u] + qy;
+            lz = hz[u] + qz;
         }
         int k1 = 0, k2 = 0;
-        double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        float v = (float)d2;
+        const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const float v = (float)d2;
         if (MODE == M_MONO || MODE == M_THETA) {
             k1 = guess1<MODE, EST>(P, v);
         } else if (MODE == M_RMU_Z) {
             k1 = guess1<M_MONO, EST>(P, v);
-            float rinv = __builtin_amdgcn_rsqf(v);
-            k2 = guess_lin(fabsf((float)dz) * rinv, P.e2a, P.e2b, P.n2m1);
+            k2 = guess_lin(fabsf((float)dz) * __builtin_amdgcn_rsqf(v), P.e2a, P.e2b, P.n2m1);
         } else if (MODE == M_RMU_MID) {
             k1 = guess1<M_MONO, EST>(P, v);
-            float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
-            float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
-            float mu = fabsf(sl) * __builtin_amdgcn_rsqf(v * ll);
-            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
+            const float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
+            const float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
+            k2 = guess_lin(fabsf(sl) * __builtin_amdgcn_rsqf(v * ll), P.e2a, P.e2b, P.n2m1);
         } else {
-            float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
-            float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
-            float rll = __builtin_amdgcn_rcpf(ll);
-            float pi2 = sl * sl * rll;
-            float sg2 = fmaxf(v - pi2, 0.0f);
-            k1 = guess_lin(__builtin_amdgcn_sqrtf(sg2), P.e1a, P.e1b, P.n1m1);
+            const float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
+            const float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
+            const float pi2 = sl * sl * __builtin_amdgcn_rcpf(ll);
+            k1 = guess_lin(__builtin_amdgcn_sqrtf(fmaxf(v - pi2, 0.0f)), P.e1a, P.e1b, P.n1m1);
             k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2m1);
         }
-        uint32_t k = classify64<MODE>(P, T1, T2, dx, dy, dz, lx, ly, lz, k1, k2);
-        if (act && k != kNoBin) hist_add(W.hist, k, P.copies, lane);
+        bin[u] = classify64<MODE>(P, T1, T2, dx, dy, dz, lx, ly, lz, k1, k2);
+        cnt[u] = act & (bin[u] != kNoBin);
     }
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++)
+        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane);
 }
 
-// Process one span (possibly split into a masked head inside the home tile
-// and an unmasked rest), in chunks that keep the LDS counters below 2^32.
+// The chunk being assembled from neighbour spans (per-lane fields in VGPRs,
+// the rest wave-uniform).
+struct Chunk {
+    uint32_t filled;   // lanes holding a neighbour
+    bool masked;       // some lane needs the j > i test
+    bool shifted;      // some lane holds a periodic image
+    uint32_t lj;       // per lane: neighbour index
+    uint32_t lcode;    // per lane: image code
+    bool lmask;        // per lane: j > i test applies
+};
+
 template <int MODE, int PREC, int EST>
-__device__ void do_span(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
-                        const double* T1, const double* T2, int lane, bool valid, uint32_t hidx,
-                        uint32_t nhome, uint32_t ts, uint32_t te, bool same, float hx32,
-                        float hy32, float hz32, double hx64, double hy64, double hz64, double sx,
-                        double sy, double sz, uint32_t j0, uint32_t j1) {
-    if (j1 <= j0) return;
-    // FP32 home point in this span's frame, and the midpoint helper hx + lc
-    float ex = hx32 - (float)sx, ey = hy32 - (float)sy, ez = hz32 - (float)sz;
-    float elx = 0.f, ely = 0.f, elz = 0.f;
-    if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-        elx = ex + P.lcx;
-        ely = ey + P.lcy;
-        elz = ez + P.lcz;
-    }
-    uint32_t a = j0;
-    if (same) {
-        // neighbours inside the home tile: only j > i; before the tile: none
-        uint32_t m0 = ts + 1u > j0 ? ts + 1u : j0;
-        uint32_t m1 = te < j1 ? te : j1;
-        if (m1 > m0) {
-            // lanes 0..(j - ts - 1) pair with neighbour j: sum of (j - ts) over the head
-            const uint64_t lo_ = m0 - ts, hi_ = m1 - 1u - ts;
-            const uint64_t pairs = (lo_ + hi_) * (hi_ - lo_ + 1u) / 2u;
-            if (W.since_flush + pairs >= 0xfffffff0ull) wave_flush<MODE, EST>(P, W, T1, T2, lane);
-            W.since_flush += pairs;
-            W.evals += pairs;
-            if (PREC == P_FP64)
-                run_span64<MODE, EST, true>(P, W, T1, T2, lane, valid, hidx, hx64, hy64, hz64, sx,
-                                            sy, sz, m0, m1);
-            else
-                run_span32<MODE, PREC, EST, true>(P, W, B1, B2, T1, T2, lane, valid, hidx, ex, ey,
-                                                  ez, elx, ely, elz, m0, m1);
+__device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
+                          const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
+                          uint32_t te) {
+    constexpr uint32_t U = 4;
+    const uint32_t nh = te - ts;
+    const bool lvalid = (uint32_t)lane < C.filled;
+    if (PREC == P_FP64) {
+        double qx = 0.0, qy = 0.0, qz = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        if (lvalid) {
+            const P64 q = P.B.p64[C.lj];
+            qx = q.x;
+            qy = q.y;
+            qz = q.z;
+            sx = shift64(C.lcode, 0, P.L);
+            sy = shift64(C.lcode, 1, P.L);
+            sz = shift64(C.lcode, 2, P.L);
         }
-        a = te > j0 ? te : j0;
+#define CUTE_RUN64(MSK, SH)                                                                     \
+    {                                                                                           \
+        uint32_t h = ts;                                                                        \
+        for (; h + U <= te; h += U)                                                             \
+            step64<MODE, EST, MSK, SH, U>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
+                                          sx, sy, sz, h);                                       \
+        for (; h < te; h++)                                                                     \
+            step64<MODE, EST, MSK, SH, 1>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
+                                          sx, sy, sz, h);                                       \
     }
-    while (a < j1) {
-        uint32_t b = (j1 - a > kChunk) ? a + kChunk : j1;
-        uint64_t pairs = (uint64_t)nhome * (uint64_t)(b - a);
-        if (W.since_flush + pairs >= 0xfffffff0ull) wave_flush<MODE, EST>(P, W, T1, T2, lane);
-        W.since_flush += pairs;
-        W.evals += pairs;
-        if (PREC == P_FP64)
-            run_span64<MODE, EST, false>(P, W, T1, T2, lane, valid, hidx, hx64, hy64, hz64, sx, sy,
-                                         sz, a, b);
-        else
-            run_span32<MODE, PREC, EST, false>(P, W, B1, B2, T1, T2, lane, valid, hidx, ex, ey, ez,
-                                               elx, ely, elz, a, b);
-        a = b;
+        if (C.masked) {
+            if (C.shifted) CUTE_RUN64(true, true) else CUTE_RUN64(true, false)
+        } else {
+            if (C.shifted) CUTE_RUN64(false, true) else CUTE_RUN64(false, false)
+        }
+#undef CUTE_RUN64
+    } else {
+        // a band constant kept in a VGPR (an fma can read only one SGPR)
+        float dA0v;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(dA0v) : "s"(P.dA0));
+        // the neighbour in the home grid's FP32 frame: q - (cA - cB) for two
+        // open grids, or its periodic image q + k L (only one of the two is
+        // ever non-zero), and q + 2 cA for the midpoint line of sight
+        float qx = 0.f, qy = 0.f, qz = 0.f, qlx = 0.f, qly = 0.f, qlz = 0.f;
+        if (lvalid) {
+            const float4 q = P.B.p32[C.lj];
+            const float Lf = (float)P.L;
+            qx = q.x - (P.offx - shift32(C.lcode, 0, Lf));
+            qy = q.y - (P.offy - shift32(C.lcode, 1, Lf));
+            qz = q.z - (P.offz - shift32(C.lcode, 2, Lf));
+            qlx = qx + P.lcx;
+            qly = qy + P.lcy;
+            qlz = qz + P.lcz;
+        }
+#define CUTE_RUN32(MSK)                                                                            \
+    {                                                                                              \
+        uint32_t h = ts;                                                                           \
+        for (; h + U <= te; h += U)                                                                \
+            step32<MODE, PREC, EST, MSK, U>(P, W, B1, B2, T1, T2, lane, lvalid, C.lmask, C.lj,     \
+                                            C.lcode, qx, qy, qz, qlx, qly, qlz, dA0v, h);          \
+        for (; h < te; h++)                                                                        \
+            step32<MODE, PREC, EST, MSK, 1>(P, W, B1, B2, T1, T2, lane, lvalid, C.lmask, C.lj,     \
+                                            C.lcode, qx, qy, qz, qlx, qly, qlz, dA0v, h);          \
+    }
+        if (C.masked) CUTE_RUN32(true) else CUTE_RUN32(false)
+#undef CUTE_RUN32
+    }
+    C.filled = 0;
+    C.masked = false;
+    C.shifted = false;
+}
+
+// Append the neighbour span [a0, a1) (image code, j > i test) to the chunk,
+// running every chunk that fills up.
+template <int MODE, int PREC, int EST>
+__device__ void feed(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
+                     const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
+                     uint32_t te, uint32_t a0, uint32_t a1, uint32_t code, bool masked) {
+    if (masked && a1 > a0) {
+        // lanes with neighbour j pair with the home points h < j: sum of (j - ts)
+        const uint64_t lo_ = a0 - ts, hi_ = a1 - 1u - ts;
+        W.evals += (lo_ + hi_) * (hi_ - lo_ + 1u) / 2u;
+    } else if (a1 > a0) {
+        W.evals += (uint64_t)(te - ts) * (a1 - a0);
+    }
+    while (a0 < a1) {
+        const uint32_t room = 64u - C.filled;
+        const uint32_t take = (a1 - a0) < room ? (a1 - a0) : room;
+        const uint32_t l = (uint32_t)lane;
+        if (l >= C.filled && l < C.filled + take) {
+            C.lj = a0 + (l - C.filled);
+            C.lcode = code;
+            C.lmask = masked;
+        }
+        C.filled += take;
+        C.masked = C.masked | masked;
+        C.shifted = C.shifted | (code != kNoShift);
+        a0 += take;
+        if (C.filled == 64u) run_chunk<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, C, ts, te);
     }
 }
 
@@ -611,44 +695,65 @@ __device__ __forceinline__ int imod(int a, int n) {
     return r < 0 ? r + n : r;
 }
 
-// Enumerate the neighbour spans of one home tile and count them.
-template <int MODE, int PREC, int EST>
-__device__ void do_tile(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
-                        const double* T1, const double* T2, int lane, const Tile& tl) {
+// Span list of one tile, built in LDS before any pair is evaluated, so that
+// the stencil's FP64 temporaries are dead while the hot loop runs.
+struct SpanBuf {
+    uint32_t* a;   // first neighbour index
+    uint32_t* b;   // one past the last
+    uint32_t* f;   // image code (low 8 bits) | j > i test (bit 8)
+    uint32_t n;    // entries (wave-uniform)
+};
+
+__device__ __forceinline__ void push_span(SpanBuf& S, int lane, uint32_t a0, uint32_t a1,
+                                          uint32_t code, bool masked) {
+    if (a1 <= a0) return;
+    if (lane == 0) {
+        S.a[S.n] = a0;
+        S.b[S.n] = a1;
+        S.f[S.n] = code | (masked ? 0x100u : 0u);
+    }
+    S.n++;
+}
+
+// Neighbour spans of the cell range [pa, pb] of row rb in the B grid. In the
+// home row of an autocorrelation the range starting at the tile's first cell
+// is split into the tile itself (pairs j > i only) and the rest.
+__device__ __forceinline__ void push_cells(SpanBuf& S, int lane, const cu32p cs, uint32_t rb,
+                                           int pa, int pb, uint32_t code, bool home_start,
+                                           uint32_t ts, uint32_t te) {
+    const uint32_t j0 = uni(cs[rb + (uint32_t)pa]);
+    const uint32_t j1 = uni(cs[rb + (uint32_t)pb + 1u]);
+    if (home_start) {
+        // points of the first cell before the tile pair with it from their own tile
+        const uint32_t m1 = te < j1 ? te : j1;
+        push_span(S, lane, ts, m1, code, true);
+        push_span(S, lane, m1 > te ? m1 : te, j1, code, false);
+    } else {
+        push_span(S, lane, j0, j1, code, false);
+    }
+}
+
+// Fill the span buffer with the neighbour spans of rows [*row, ...) of the
+// tile's stencil (Sec. 3.3: the cells within r_max of the tile), stopping
+// before the buffer could overflow. Returns true when every row is done.
+__device__ bool gen_spans(const CountArgs& P, const Tile& tl, int lane, SpanBuf& S, int* row) {
     const uint32_t ts = tl.start, te = tl.end;
-    const uint32_t nhome = te - ts;
     const int c0 = (int)(tl.c0c1 & 0xffffu), c1 = (int)(tl.c0c1 >> 16);
     const GridView& A = P.A;
     const GridView& B = P.B;
     const int cy = (int)(tl.row % (uint32_t)A.ny), cz = (int)(tl.row / (uint32_t)A.ny);
-    const bool valid = (uint32_t)lane < nhome;
-    const uint32_t hidx = ts + (uint32_t)lane;
-    float hx32 = 0.f, hy32 = 0.f, hz32 = 0.f;
-    double hx64 = 0.0, hy64 = 0.0, hz64 = 0.0;
-    if (valid) {
-        if (PREC == P_FP64) {
-            P64 p = A.p64[hidx];
-            hx64 = p.x;
-            hy64 = p.y;
-            hz64 = p.z;
-        } else {
-            float4 p = A.p32[hidx];
-            hx32 = p.x + P.offx;
-            hy32 = p.y + P.offy;
-            hz32 = p.z + P.offz;
-        }
-    }
-    W.tiles++;
-    const double R = P.Rs;
+    const cu32p cs = (cu32p)(const void*)B.cstart;
+    S.n = 0;
+    const uint32_t room = kSpanCap - 3;
 
     if (P.geom == CUTE_GEOM_SPHERE) {
         // tile pixel block: phi in [c0, c1+1) * ax, cos theta in one band
         const double zlo = A.oy + cy * A.ay, zhi = zlo + A.ay;
         const double zl = fmax(-1.0, fmin(1.0, zlo)), zh = fmax(-1.0, fmin(1.0, zhi));
         const double th_lo = acos(zh), th_hi = acos(zl);
-        const double ts_ = P.th_s;
-        const double zn_hi = (th_lo - ts_ <= 0.0) ? 1.0 : cos(th_lo - ts_);
-        const double zn_lo = (th_hi + ts_ >= kPi) ? -1.0 : cos(th_hi + ts_);
+        const double ths = P.th_s;
+        const double zn_hi = (th_lo - ths <= 0.0) ? 1.0 : cos(th_lo - ths);
+        const double zn_lo = (th_hi + ths >= kPi) ? -1.0 : cos(th_hi + ths);
         int b0 = (int)floor((zn_lo - B.oy) / B.ay) - 1, b1 = (int)floor((zn_hi - B.oy) / B.ay) + 1;
         b0 = clampi(b0, 0, B.ny - 1);
         b1 = clampi(b1, 0, B.ny - 1);
@@ -657,77 +762,54 @@ __device__ void do_tile(const CountArgs& P, WaveState& W, const float2* B1, cons
         const double zmax2 = fmax(zl * zl, zh * zh);
         const double smin = sqrt(fmax(0.0, 1.0 - zmax2));
         bool full = !(P.sin_th_s < smin * (1.0 - 1e-9)) || (P.th_s >= 0.5 * kPi);
-        double hw = full ? 0.0 : asin(P.sin_th_s / smin) * (1.0 + 1e-9) + 1e-12;
+        const double hw = full ? 0.0 : asin(P.sin_th_s / smin) * (1.0 + 1e-9) + 1e-12;
         const double phlo = c0 * A.ax - hw, phhi = (c1 + 1) * A.ax + hw;
-        int x0 = (int)floor(phlo / B.ax) - 1, x1 = (int)floor(phhi / B.ax) + 1;
+        const int x0 = (int)floor(phlo / B.ax) - 1, x1 = (int)floor(phhi / B.ax) + 1;
         if (x1 - x0 + 1 >= B.nx) full = true;
-        for (int by = b0; by <= b1; by++) {
+        for (int by = b0 + *row; by <= b1; by++) {
+            if (S.n > room) {
+                *row = by - b0;
+                return false;
+            }
             const int byu = unii(by);
             const bool same = P.is_auto && byu == cy;
             if (P.is_auto && byu < cy) continue;
             const uint32_t rb = (uint32_t)byu * (uint32_t)B.nx;
-            int pa[2][2];
-            int np = 0;
             if (same) {
-                // index rule inside the home band: partners with larger index,
-                // i.e. cells >= c0 up to the right reach, plus the left reach
-                // that wraps past phi = 2 pi onto the band's last cells
-                if (full) {
-                    pa[np][0] = c0;
-                    pa[np][1] = B.nx - 1;
-                    np++;
-                } else {
-                    int r1 = x1 < B.nx - 1 ? x1 : B.nx - 1;
-                    int s2 = x0 < 0 ? x0 + B.nx : B.nx;  // start of wrapped left part
-                    if (s2 <= r1 + 1) {
-                        pa[np][0] = c0;
-                        pa[np][1] = B.nx - 1;
-                        np++;
-                    } else {
-                        pa[np][0] = c0;
-                        pa[np][1] = r1;
-                        np++;
-                        if (s2 <= B.nx - 1) {
-                            pa[np][0] = s2;
-                            pa[np][1] = B.nx - 1;
-                            np++;
-                        }
+                // index rule inside the home band: partners with a larger
+                // index, i.e. cells >= c0 up to the right reach, plus the left
+                // reach that wraps past phi = 2 pi onto the band's last cells
+                int p0b = B.nx - 1, p1a = 0, p1b = -1;
+                if (!full) {
+                    const int r1 = x1 < B.nx - 1 ? x1 : B.nx - 1;
+                    const int s2 = x0 < 0 ? x0 + B.nx : B.nx;
+                    if (s2 > r1 + 1) {
+                        p0b = r1;
+                        p1a = s2;
+                        p1b = B.nx - 1;
                     }
                 }
+                push_cells(S, lane, cs, rb, c0, p0b, kNoShift, true, ts, te);
+                if (p1b >= p1a) push_cells(S, lane, cs, rb, p1a, p1b, kNoShift, false, ts, te);
             } else if (full) {
-                pa[0][0] = 0;
-                pa[0][1] = B.nx - 1;
-                np = 1;
+                push_cells(S, lane, cs, rb, 0, B.nx - 1, kNoShift, false, ts, te);
             } else {
                 // cyclic range [x0, x1] (length < nx) split at the phi wrap
-                int a0 = imod(x0, B.nx);
-                int len = x1 - x0 + 1;
+                const int a0 = imod(x0, B.nx);
+                const int len = x1 - x0 + 1;
                 if (a0 + len <= B.nx) {
-                    pa[0][0] = a0;
-                    pa[0][1] = a0 + len - 1;
-                    np = 1;
+                    push_cells(S, lane, cs, rb, a0, a0 + len - 1, kNoShift, false, ts, te);
                 } else {
-                    pa[0][0] = a0;
-                    pa[0][1] = B.nx - 1;
-                    pa[1][0] = 0;
-                    pa[1][1] = a0 + len - 1 - B.nx;
-                    np = 2;
+                    push_cells(S, lane, cs, rb, a0, B.nx - 1, kNoShift, false, ts, te);
+                    push_cells(S, lane, cs, rb, 0, a0 + len - 1 - B.nx, kNoShift, false, ts, te);
                 }
             }
-            for (int q = 0; q < np; q++) {
-                const cu32p cs = (cu32p)(const void*)B.cstart;
-                uint32_t j0 = uni(cs[rb + (uint32_t)pa[q][0]]);
-                uint32_t j1 = uni(cs[rb + (uint32_t)pa[q][1] + 1u]);
-                const bool chk = same && pa[q][0] == c0;
-                do_span<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, valid, hidx, nhome, ts, te,
-                                         chk, hx32, hy32, hz32, hx64, hy64, hz64, 0.0, 0.0, 0.0, j0,
-                                         j1);
-            }
         }
-        return;
+        return true;
     }
 
     // 3-D boxes: the tile box, grown by R, selects rows of neighbour cells
+    const double R = P.Rs;
     const double xlo = A.ox + c0 * A.ax, xhi = A.ox + (c1 + 1) * A.ax;
     const double ylo = A.oy + cy * A.ay, yhi = ylo + A.ay;
     const double zlo = A.oz + cz * A.az, zhi = zlo + A.az;
@@ -739,63 +821,89 @@ __device__ void do_tile(const CountArgs& P, WaveState& W, const float2* B1, cons
         z0 = clampi(z0, 0, B.nz - 1);
         z1 = clampi(z1, 0, B.nz - 1);
     }
+    const int nyr = y1 - y0 + 1;
+    const int nrows = nyr * (z1 - z0 + 1);
     const double R2 = R * R;
-    for (int bz = z0; bz <= z1; bz++) {
-        for (int by = y0; by <= y1; by++) {
-            const int bzu = unii(bz), byu = unii(by);
-            bool same = false;
-            if (P.is_auto) {
-                const int oz_ = bzu - cz, oy_ = byu - cy;
-                if (oz_ < 0 || (oz_ == 0 && oy_ < 0)) continue;
-                same = (oz_ == 0 && oy_ == 0);
-            }
-            // distance in y and z between the tile box and this row of cells
-            const double rylo = B.oy + byu * B.ay, ryhi = rylo + B.ay;
-            const double rzlo = B.oz + bzu * B.az, rzhi = rzlo + B.az;
-            const double dy = fmax(0.0, fmax(rylo - yhi, ylo - ryhi));
-            const double dz = fmax(0.0, fmax(rzlo - zhi, zlo - rzhi));
-            const double rem = R2 - dy * dy - dz * dz;
-            if (rem <= 0.0) continue;
-            const double w = sqrt(rem);
-            int x0 = (int)floor((xlo - w - B.ox) / B.ax), x1 = (int)floor((xhi + w - B.ox) / B.ax);
-            if (same && x0 < c0) x0 = c0;
-            double sy = 0.0, sz = 0.0;
-            int ry = byu, rz = bzu;
-            if (P.periodic) {
-                const int ky = floordiv(byu, B.ny), kz = floordiv(bzu, B.nz);
-                ry = byu - ky * B.ny;
-                rz = bzu - kz * B.nz;
-                sy = ky * P.L;
-                sz = kz * P.L;
-            } else {
-                x0 = x0 < 0 ? 0 : x0;
-                x1 = x1 > B.nx - 1 ? B.nx - 1 : x1;
-                if (x0 > x1) continue;
-            }
-            const uint32_t rb = (uint32_t)B.nx * ((uint32_t)ry + (uint32_t)B.ny * (uint32_t)rz);
-            // split [x0, x1] at periodic wraps (at most two pieces)
-            int a0 = x0;
-            while (a0 <= x1) {
-                const int kx = P.periodic ? floordiv(a0, B.nx) : 0;
-                const int lim = P.periodic ? (kx + 1) * B.nx - 1 : x1;
-                const int a1 = x1 < lim ? x1 : lim;
-                const int u0 = a0 - kx * B.nx, u1 = a1 - kx * B.nx;
-                const cu32p cs = (cu32p)(const void*)B.cstart;
-                uint32_t j0 = uni(cs[rb + (uint32_t)u0]);
-                uint32_t j1 = uni(cs[rb + (uint32_t)u1 + 1u]);
-                const double sx = kx * P.L;
-                const bool chk = same && kx == 0 && a0 == c0;
-                do_span<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, valid, hidx, nhome, ts, te,
-                                         chk, hx32, hy32, hz32, hx64, hy64, hz64, sx, sy, sz, j0,
-                                         j1);
-                a0 = a1 + 1;
-            }
+    for (int r = *row; r < nrows; r++) {
+        if (S.n > room) {
+            *row = r;
+            return false;
+        }
+        const int bzu = unii(z0 + r / nyr), byu = unii(y0 + r % nyr);
+        bool same = false;
+        if (P.is_auto) {
+            const int oz_ = bzu - cz, oy_ = byu - cy;
+            if (oz_ < 0 || (oz_ == 0 && oy_ < 0)) continue;
+            same = (oz_ == 0 && oy_ == 0);
+        }
+        // distance in y and z between the tile box and this row of cells
+        const double rylo = B.oy + byu * B.ay, ryhi = rylo + B.ay;
+        const double rzlo = B.oz + bzu * B.az, rzhi = rzlo + B.az;
+        const double dy = fmax(0.0, fmax(rylo - yhi, ylo - ryhi));
+        const double dz = fmax(0.0, fmax(rzlo - zhi, zlo - rzhi));
+        const double rem = R2 - dy * dy - dz * dz;
+        if (rem <= 0.0) continue;
+        const double w = sqrt(rem);
+        int x0 = (int)floor((xlo - w - B.ox) / B.ax), x1 = (int)floor((xhi + w - B.ox) / B.ax);
+        if (same && x0 < c0) x0 = c0;
+        int ry = byu, rz = bzu, ky = 0, kz = 0;
+        if (P.periodic) {
+            ky = floordiv(byu, B.ny);
+            kz = floordiv(bzu, B.nz);
+            ry = byu - ky * B.ny;
+            rz = bzu - kz * B.nz;
+        } else {
+            x0 = x0 < 0 ? 0 : x0;
+            x1 = x1 > B.nx - 1 ? B.nx - 1 : x1;
+            if (x0 > x1) continue;
+        }
+        const uint32_t rb = (uint32_t)B.nx * ((uint32_t)ry + (uint32_t)B.ny * (uint32_t)rz);
+        // split [x0, x1] at periodic wraps (at most two pieces)
+        int a0 = x0;
+        while (a0 <= x1) {
+            const int kx = P.periodic ? floordiv(a0, B.nx) : 0;
+            const int lim = P.periodic ? (kx + 1) * B.nx - 1 : x1;
+            const int a1 = x1 < lim ? x1 : lim;
+            const uint32_t code =
+                (uint32_t)(kx + 1) | ((uint32_t)(ky + 1) << 2) | ((uint32_t)(kz + 1) << 4);
+            push_cells(S, lane, cs, rb, a0 - kx * B.nx, a1 - kx * B.nx, code,
+                       same && kx == 0 && a0 == c0, ts, te);
+            a0 = a1 + 1;
         }
     }
+    return true;
 }
 
+// Count the pairs of one home tile: spans are generated into the LDS span
+// buffer, then fed chunk by chunk to the hot loop.
 template <int MODE, int PREC, int EST>
-__global__ __launch_bounds__(256) void k_count(CountArgs P) {
+__device__ void do_tile(const CountArgs& P, WaveState& W, SpanBuf& S, const float2* B1,
+                        const float2* B2, const double* T1, const double* T2, int lane,
+                        const Tile& tl) {
+    W.tiles++;
+    Chunk C;
+    C.filled = 0;
+    C.masked = false;
+    C.shifted = false;
+    C.lj = 0;
+    C.lcode = kNoShift;
+    C.lmask = false;
+    int row = 0;
+    bool done = false;
+    while (!done) {
+        done = gen_spans(P, tl, lane, S, &row);
+        for (uint32_t k = 0; k < S.n; k++) {
+            const uint32_t a0 = uni(S.a[k]), a1 = uni(S.b[k]), f = uni(S.f[k]);
+            feed<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end, a0, a1,
+                                  f & 0xffu, (f & 0x100u) != 0u);
+        }
+    }
+    if (C.filled) run_chunk<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end);
+}
+
+// Four 4-wave workgroups per CU: the register budget stays at 128 VGPRs.
+template <int MODE, int PREC, int EST>
+__global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -806,25 +914,33 @@ __global__ __launch_bounds__(256) void k_count(CountArgs P) {
     double* T2 = T1 + (n1 + 1);
     float2* B1 = reinterpret_cast<float2*>(T2 + (n2p + 1));
     float2* B2 = B1 + n1;
-    uint32_t* hist0 = reinterpret_cast<uint32_t*>(B2 + (n2p > 0 ? n2p : 1));
-    uint32_t* q0 = hist0 + (size_t)nwaves * P.hist_words;
+    unsigned long long* hist0 = reinterpret_cast<unsigned long long*>(B2 + (n2p > 0 ? n2p : 1));
+    uint32_t* q0 = reinterpret_cast<uint32_t*>(hist0 + P.hist_words);
+    unsigned long long* rs0 = reinterpret_cast<unsigned long long*>(q0 + (size_t)nwaves * 3 * kQCap);
+    uint32_t* sp0 = reinterpret_cast<uint32_t*>(rs0 + 2 * nwaves);
     for (int i = threadIdx.x; i <= n1; i += blockDim.x) T1[i] = P.T1[i];
     for (int i = threadIdx.x; i <= n2p; i += blockDim.x) T2[i] = n2p ? P.T2[i] : 0.0;
     if (PREC != P_FP64) {
         for (int i = threadIdx.x; i < n1; i += blockDim.x) B1[i] = P.band1[i];
         for (int i = threadIdx.x; i < n2p; i += blockDim.x) B2[i] = P.band2[i];
     }
-    for (int i = threadIdx.x; i < nwaves * P.hist_words; i += blockDim.x) hist0[i] = 0u;
+    for (int i = threadIdx.x; i < P.hist_words; i += blockDim.x) hist0[i] = 0ull;
+    for (int i = threadIdx.x; i < 2 * nwaves; i += blockDim.x) rs0[i] = 0ull;
     __syncthreads();
 
     WaveState W;
-    W.hist = hist0 + (size_t)wave * P.hist_words;
+    W.hist = hist0;
     W.qi = q0 + (size_t)wave * 3 * kQCap;
     W.qj = W.qi + kQCap;
-    W.qt = W.qj + kQCap;
+    W.qc = W.qj + kQCap;
+    W.rstat = rs0 + 2 * wave;
     W.tail = 0;
-    W.since_flush = 0;
-    W.evals = W.retests = W.flips = W.tiles = 0;
+    W.evals = W.tiles = 0;
+    SpanBuf S;
+    S.a = sp0 + (size_t)wave * 3 * kSpanCap;
+    S.b = S.a + kSpanCap;
+    S.f = S.b + kSpanCap;
+    S.n = 0;
 
     for (;;) {
         uint32_t t = 0;
@@ -837,23 +953,23 @@ __global__ __launch_bounds__(256) void k_count(CountArgs P) {
         tl.end = uni(tp[4 * t + 1]);
         tl.row = uni(tp[4 * t + 2]);
         tl.c0c1 = uni(tp[4 * t + 3]);
-        do_tile<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, tl);
+        do_tile<MODE, PREC, EST>(P, W, S, B1, B2, T1, T2, lane, tl);
     }
-    if (PREC == P_FP32E) drain_queue<MODE, EST>(P, W, T1, T2, lane, true);
+    if (PREC == P_FP32E)
+        W.tail = drain_queue<MODE, EST>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,
+                                        W.tail, true);
     if (lane == 0) {
         atomicAdd(&P.stats[0], (unsigned long long)W.evals);
-        atomicAdd(&P.stats[1], (unsigned long long)W.retests);
-        atomicAdd(&P.stats[2], (unsigned long long)W.flips);
+        atomicAdd(&P.stats[1], W.rstat[0]);
+        atomicAdd(&P.stats[2], W.rstat[1]);
         atomicAdd(&P.stats[3], (unsigned long long)W.tiles);
     }
     __syncthreads();
-    // sum the waves' histograms and their copies, then one atomic per bin
+    // sum the copies, then one global atomic per non-empty bin
     for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) {
         uint64_t s = 0;
-        for (int w = 0; w < nwaves; w++) {
-            const uint32_t* h = hist0 + (size_t)w * P.hist_words + (size_t)b * P.copies;
-            for (int c = 0; c < P.copies; c++) s += h[c];
-        }
+        const unsigned long long* hh = hist0 + (size_t)b * P.copies;
+        for (int c = 0; c < P.copies; c++) s += hh[c];
         if (s) atomicAdd(&P.counts[b], (unsigned long long)s);
     }
 }
@@ -912,9 +1028,10 @@ cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int
     }
 }
 
-// Home tiles: each row of cells is cut into runs of at most 64 points whose
-// x-extent stays within max_w cells (so that periodic stencils never wrap
-// onto themselves). One thread walks one row.
+// Home tiles: each row of cells is cut into runs of at most kTileMax points
+// whose x-extent stays within max_w cells (so that periodic stencils never
+// wrap onto themselves); a cell with more points is split. One thread walks
+// one row.
 __global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict__ cstart, int nx,
                                                      int nrows, int max_w, uint32_t* __restrict__ ntile) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -925,12 +1042,12 @@ __global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict_
     for (int c = 0; c < nx; c++) {
         uint32_t left = cs[c + 1] - cs[c];
         while (left > 0) {
-            if (fill == 0 || fill == 64u || c - first + 1 > max_w) {
+            if (fill == 0 || fill == kTileMax || c - first + 1 > max_w) {
                 cnt++;
                 fill = 0;
                 first = c;
             }
-            uint32_t take = 64u - fill < left ? 64u - fill : left;
+            uint32_t take = kTileMax - fill < left ? kTileMax - fill : left;
             fill += take;
             left -= take;
         }
@@ -954,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
         uint32_t pos = cs[c];
         uint32_t left = cs[c + 1] - cs[c];
         while (left > 0) {
-            if (!open || fill == 64u || c - first + 1 > max_w) {
+            if (!open || fill == kTileMax || c - first + 1 > max_w) {
                 if (open) tiles[o++] = cur;
                 open = true;
                 fill = 0;
@@ -964,7 +1081,7 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
                 cur.row = (uint32_t)r;
                 cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
             }
-            uint32_t take = 64u - fill < left ? 64u - fill : left;
+            uint32_t take = kTileMax - fill < left ? kTileMax - fill : left;
             fill += take;
             left -= take;
             pos += take;

@@ -44,6 +44,7 @@ struct cute_grid_impl;
 
 // Everything a count kernel needs, passed by value.
 struct CountArgs {
+    const CountArgs* self;          // a copy of these arguments in device memory
     GridView A, B;
     const Tile* tiles;
     uint32_t ntiles;
@@ -61,7 +62,6 @@ struct CountArgs {
     float n1m1, n2m1;               // n1 - 1 and n2 - 1 as floats (estimate clamps)
     int copies;                     // LDS histogram copies per wave (power of two)
     int hist_words;                 // nbins * copies
-    uint32_t flush_budget;          // per-wave candidate pairs between flushes
     // FP32 geometry constants
     float offx, offy, offz;         // FP32(cA - cB), added to home points (open boxes)
     float lcx, lcy, lcz;            // FP32(2 cB): l = home_eff + q + lc (midpoint LOS)

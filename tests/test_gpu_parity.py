@@ -94,6 +94,31 @@ def test_mono_periodic_config1_full_size():
         np.testing.assert_array_equal(got, np.array(g["counts"], dtype=np.uint64))
 
 
+def test_rmu_dd_full_size_benchmark_workload():
+    """The benchmark workload at its full size (1e6 clustered points, r-mu
+    40 x 50 bins) in the benchmark's launch configuration, against the
+    oracle's counts stored by tests/golden/make_golden.py."""
+    import torch
+    with open(os.path.join(GOLDEN, "c2_dd_rmu.json")) as f:
+        g = json.load(f)
+    d, _ = catalogs.config2()
+    assert catalogs.sha256_of(d) == g["sha256"], "generator output changed"
+    want = np.array(g["counts"], dtype=np.uint64)
+    dev = torch.device("cuda:0")
+    xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (d.x, d.y, d.z)]
+    bn = cute.Binning(cute.BIN_RMU, np.array(g["r_edges"]), np.array(g["mu_edges"]), los=cute.LOS_Z)
+    out = torch.zeros(bn.nbins, dtype=torch.int64, device=dev)
+    for prec in EXACT:
+        say("case c2-full prec", prec)
+        grid = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0)
+        cute.count_pairs(grid, None, bn, prec, out=out)
+        np.testing.assert_array_equal(out.cpu().numpy().astype(np.uint64), want)
+    # the FP32-only path misclassifies only a few pairs per million
+    cute.count_pairs(grid, None, bn, cute.PREC_FP32_ONLY, out=out)
+    l1 = int(np.abs(out.cpu().numpy() - want.astype(np.int64)).sum())
+    assert l1 < 1e-4 * int(want.sum())
+
+
 @pytest.mark.parametrize("cell", [0.0, 7.0, 33.0])
 def test_mono_open_log_bins(cell):
     d, r = catalogs.config2(n_centres=120, per_blob=40, n_rand=8000, box=250.0)

@@ -59,6 +59,21 @@ def cpu_baseline(d, target_s=15.0):
                       "catalog, same r-mu binning, %.1f s" % (pairs, n2, dt)}
 
 
+def committed_traffic():
+    """HBM bytes per count launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_count_rmu_c2_dd.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    with open(os.path.join(ROOT, prof["kernel_source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != prof["kernel_source_sha256"]:
+            return None
+    return prof["fp32_edge"]["hbm_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,10 +125,11 @@ def main():
         return dt, sts
 
     if args.copy_probe_mib:
-        # a plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters
+        # a plain streaming kernel of known traffic (reads and writes copy_probe_mib
+        # MiB each), for scaling the FETCH_SIZE / WRITE_SIZE counters
         src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         log("bench: copy probe of %d MiB done" % args.copy_probe_mib)
         del src, dst
@@ -180,7 +196,8 @@ def main():
         "speedup_fp32edge_vs_fp64": round(ms64 / ms32, 3),
         "kernel_speedup_fp32edge_vs_fp64": round(kern64_ms / kern_ms, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                     "unit": "Tlane-op/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "Tlane-op/s", "frac": round(achieved / peak, 4),
+                     "traffic": committed_traffic(),
                      "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
     }
     if not args.no_cpu_baseline:

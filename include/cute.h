@@ -162,6 +162,76 @@ cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);
 
+/* ---- Batched counts ---------------------------------------------------------
+ * The error analyses of Sec. 4 (Fig. 5) need the same pair counts over many
+ * catalogs: hundreds of mock catalogs, or one catalog with one region left out
+ * at a time (jackknife). A batch counts many items in one persistent launch per
+ * distinct binning; all launches of a batch are captured once in a HIP graph.
+ *
+ * One item: the pairs between grids a and b (b NULL or a: the autocorrelation
+ * of a, pairs i < j) in which neither point is masked, binned by *bins. The
+ * counts equal those of cute_count_pairs on the catalogs with the masked points
+ * removed (bit-exact for FP64 and FP32_EDGE).
+ * mask_a: NULL, or a->n bytes in a's input order; a nonzero byte leaves the
+ *   point out. Read when the batch is created (later changes are not seen).
+ * mask_b: the same for b; ignored for an autocorrelation (mask_a applies to
+ *   both sides).
+ * masks_on_device: nonzero if the masks are device pointers. */
+typedef struct {
+    const cute_grid* a;
+    const cute_grid* b;
+    const uint8_t* mask_a;
+    const uint8_t* mask_b;
+    int32_t masks_on_device;
+    const cute_binning* bins;
+} cute_batch_item;
+
+typedef struct cute_batch cute_batch;
+
+/* Plan a batch: validate every item (the errors of cute_count_pairs, plus
+ * CUTE_E_INVALID_ARG for n_items < 1 or a NULL item field), build the home
+ * tiles, convert the masks, order the work by estimated cost (largest item
+ * first), allocate the device counts and capture the launches in a graph.
+ * The grids must stay alive and unchanged until cute_batch_free. stream is
+ * used for the set-up work, which is complete when the call returns. */
+cute_status cute_batch_create(const cute_batch_item* items, int32_t n_items,
+                              cute_precision prec, void* stream, cute_batch** out);
+
+/* Count every item into the batch's device counts (overwritten) on stream.
+ * flags: CUTE_BATCH_GRAPH launches the captured graph; CUTE_BATCH_EAGER
+ * enqueues the same kernels directly (capturable by the caller: no
+ * allocation, no memset, no synchronisation). Asynchronous. Runs of one batch
+ * must not overlap (they share the counts). */
+enum { CUTE_BATCH_GRAPH = 0, CUTE_BATCH_EAGER = 1 };
+cute_status cute_batch_run(cute_batch* b, int32_t flags, void* stream);
+
+/* Copy the counts of item (n1 * max(n2, 1) uint64), or of every item
+ * concatenated in item order if item == -1, to out (device memory if
+ * on_device). Synchronises stream when out is host memory. */
+cute_status cute_batch_counts(const cute_batch* b, int32_t item, uint64_t* out, int32_t on_device,
+                              void* stream);
+
+/* Number of count words of item (or of all items if item == -1), and the
+ * offset of item's counts in the concatenation. */
+cute_status cute_batch_layout(const cute_batch* b, int32_t item, int64_t* words, int64_t* offset);
+
+/* Work counters of the last run of item (or the sum over items if
+ * item == -1): pair_evals, pairs_in_range, retests, flips, tiles; ms_count is
+ * 0 (time runs with events on the stream). Synchronises stream.
+ * CUTE_E_INTERNAL if a run left tiles unprocessed. */
+cute_status cute_batch_stats(const cute_batch* b, int32_t item, cute_count_stats* st, void* stream);
+
+/* Release a batch (NULL is allowed). Waits for the device. */
+void cute_batch_free(cute_batch* b);
+
+/* One-shot batch: create, run once, copy each item's counts to counts[i]
+ * (device pointers if counts_on_device), free. st (nullable) receives the sum
+ * over items, with ms_count the device time of the run. */
+cute_status cute_count_pairs_batched(const cute_batch_item* items, int32_t n_items,
+                                     cute_precision prec, uint64_t* const* counts,
+                                     int32_t counts_on_device, cute_count_stats* st,
+                                     void* stream);
+
 /* Estimator of Sec. 2.2 per bin (xi has the shape of the counts).
  * NATURAL: dd, rr; LS: dd, dr, rr; BOX: dd only (MONO binning, periodic
  * volume box_size^3, expected count N(N-1)/2 * V_shell / L^3 with the exact

@@ -24,7 +24,11 @@ LOS_Z, LOS_MIDPOINT = range(2)
 PREC_FP64, PREC_FP32_EDGE, PREC_FP32_ONLY = range(3)
 EST_NATURAL, EST_LS, EST_BOX = range(3)
 
+BATCH_GRAPH, BATCH_EAGER = range(2)
+
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
+            "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
+            "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
 
@@ -53,6 +57,12 @@ class CountStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CBatchItem(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("mask_a", ctypes.c_void_p),
+                ("mask_b", ctypes.c_void_p), ("masks_on_device", ctypes.c_int32),
+                ("bins", ctypes.POINTER(CBinning))]
 
 
 class GridInfo(ctypes.Structure):
@@ -88,6 +98,24 @@ def load():
     lib.cute_count_pairs.restype = ctypes.c_int
     lib.cute_count_pairs.argtypes = [vp, vp, ctypes.POINTER(CBinning), ctypes.c_int, vp,
                                      ctypes.c_int32, ctypes.POINTER(CountStats), vp]
+    ip = ctypes.POINTER(ctypes.c_int64)
+    lib.cute_batch_create.restype = ctypes.c_int
+    lib.cute_batch_create.argtypes = [ctypes.POINTER(CBatchItem), ctypes.c_int32, ctypes.c_int, vp,
+                                      ctypes.POINTER(vp)]
+    lib.cute_batch_run.restype = ctypes.c_int
+    lib.cute_batch_run.argtypes = [vp, ctypes.c_int32, vp]
+    lib.cute_batch_counts.restype = ctypes.c_int
+    lib.cute_batch_counts.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp]
+    lib.cute_batch_layout.restype = ctypes.c_int
+    lib.cute_batch_layout.argtypes = [vp, ctypes.c_int32, ip, ip]
+    lib.cute_batch_stats.restype = ctypes.c_int
+    lib.cute_batch_stats.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(CountStats), vp]
+    lib.cute_batch_free.restype = None
+    lib.cute_batch_free.argtypes = [vp]
+    lib.cute_count_pairs_batched.restype = ctypes.c_int
+    lib.cute_count_pairs_batched.argtypes = [ctypes.POINTER(CBatchItem), ctypes.c_int32,
+                                             ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int32,
+                                             ctypes.POINTER(CountStats), vp]
     lib.cute_xi_estimate.restype = ctypes.c_int
     lib.cute_xi_estimate.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(CBinning), ctypes.c_double, dp]
@@ -246,6 +274,127 @@ def count_pairs(a: Grid, b: Grid | None, binning: Binning, prec: int = PREC_FP32
                               int(prec), ptr, on_dev, ctypes.byref(st), _stream_handle(stream))
     _check(rc)
     res = counts.reshape(binning.shape) if out is None else counts
+    return (res, st.as_dict()) if with_stats else res
+
+
+@dataclass
+class BatchItem:
+    """One item of a batched count (cute_batch_item): the pairs of grids a and
+    b (None: autocorrelation of a) with no masked point. Masks are uint8 arrays
+    in the grid's input order (numpy on the host or torch on the device); a
+    nonzero entry leaves the point out."""
+    a: Grid
+    b: Grid | None
+    binning: Binning
+    mask_a: object = None
+    mask_b: object = None
+
+
+def _mask_ptr(m, n):
+    if m is None:
+        return None, None
+    try:
+        import torch
+        if isinstance(m, torch.Tensor):
+            t = m.contiguous()
+            if t.dtype not in (torch.uint8, torch.bool) or t.numel() != n:
+                raise ValueError("a mask must be uint8/bool with one entry per point")
+            return t, bool(t.is_cuda)
+    except ImportError:  # pragma: no cover
+        pass
+    a = np.ascontiguousarray(m, dtype=np.uint8)
+    if a.size != n:
+        raise ValueError("a mask must have one entry per point")
+    return a, False
+
+
+def _c_items(items):
+    """ctypes array of cute_batch_item plus the objects it points into."""
+    keep = []
+    arr = (CBatchItem * len(items))()
+    for k, it in enumerate(items):
+        cb = it.binning.c()
+        keep.append((it.binning, cb))
+        ma, da = _mask_ptr(it.mask_a, it.a.n)
+        mb, db = _mask_ptr(it.mask_b, (it.b or it.a).n)
+        if ma is not None and mb is not None and da != db:
+            raise ValueError("both masks of an item must be on the host or both on the device")
+        on_dev = bool(da) if ma is not None else bool(db)
+        keep.extend([ma, mb])
+
+        def addr(m):
+            if m is None:
+                return None
+            return m.data_ptr() if hasattr(m, "data_ptr") else m.ctypes.data
+
+        arr[k] = CBatchItem(it.a.handle, None if it.b is None else it.b.handle, addr(ma), addr(mb),
+                            1 if on_dev else 0, ctypes.pointer(cb))
+    return arr, keep
+
+
+class Batch:
+    """cute_batch: many pair counts planned once, run as one graph launch."""
+
+    def __init__(self, items, prec: int = PREC_FP32_EDGE, stream=None):
+        lib = load()
+        self.items = list(items)
+        arr, keep = _c_items(self.items)
+        h = ctypes.c_void_p()
+        _check(lib.cute_batch_create(arr, len(self.items), int(prec), _stream_handle(stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self._grids = [(it.a, it.b) for it in self.items]   # grids must outlive the batch
+
+    def run(self, stream=None, eager: bool = False):
+        _check(load().cute_batch_run(self._h, BATCH_EAGER if eager else BATCH_GRAPH,
+                                     _stream_handle(stream)))
+
+    def layout(self, item: int = -1):
+        w, o = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().cute_batch_layout(self._h, int(item), ctypes.byref(w), ctypes.byref(o)))
+        return w.value, o.value
+
+    def counts(self, item: int = -1, out=None, stream=None):
+        """Counts of item (shaped like its binning), or all items concatenated
+        (item=-1), as numpy; or copied into the device tensor ``out``."""
+        w, _ = self.layout(item)
+        if out is not None:
+            _check(load().cute_batch_counts(self._h, int(item), out.data_ptr(), 1,
+                                            _stream_handle(stream)))
+            return out
+        c = np.zeros(w, dtype=np.uint64)
+        _check(load().cute_batch_counts(self._h, int(item), c.ctypes.data, 0,
+                                        _stream_handle(stream)))
+        return c.reshape(self.items[item].binning.shape) if item >= 0 else c
+
+    def stats(self, item: int = -1, stream=None):
+        st = CountStats()
+        _check(load().cute_batch_stats(self._h, int(item), ctypes.byref(st), _stream_handle(stream)))
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            load().cute_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count_pairs_batched(items, prec: int = PREC_FP32_EDGE, stream=None, with_stats: bool = False):
+    """cute_count_pairs_batched: a list of numpy uint64 counts, one per item."""
+    lib = load()
+    items = list(items)
+    arr, keep = _c_items(items)
+    outs = [np.zeros(it.binning.nbins, dtype=np.uint64) for it in items]
+    ptrs = (ctypes.c_void_p * len(items))(*[o.ctypes.data for o in outs])
+    st = CountStats()
+    _check(lib.cute_count_pairs_batched(arr, len(items), int(prec), ptrs, 0, ctypes.byref(st),
+                                        _stream_handle(stream)))
+    res = [o.reshape(it.binning.shape) for o, it in zip(outs, items)]
     return (res, st.as_dict()) if with_stats else res
 
 

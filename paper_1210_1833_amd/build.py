@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["grid.hip", "count_kernels.hip", "capi.hip"]
+SOURCES = ["grid.hip", "count_kernels.hip", "batch_kernels.hip", "plan.hip", "capi.hip", "batch.hip"]
 LIB = os.path.join(HERE, "libcute.so")
 BUILD = os.path.join(HERE, "_build")
 
@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 # -packed-fp32-ops is switched off for every kernel (no packed FP32 math).
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+         "-Wall", "-Wno-unused-function", "-Wno-bitwise-instead-of-logical", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def build(verbose: bool = False, jobs: int = 3) -> str:

@@ -1,13 +1,13 @@
 // Pair-count kernels for gfx950.
 //
 // One wavefront owns one home tile at a time (a run of up to 64 sorted points
-// inside one row of cells, one point per lane) and walks the neighbour cells
-// of Sec. 3.3 as contiguous spans of the other catalog. The neighbour point
-// is wave-uniform, so its coordinates arrive through scalar loads and enter
-// the VALU as scalar operands; every lane evaluates its own pair. Counts go
-// to a per-wave LDS histogram (several interleaved copies, one per lane
-// group, so that lanes hitting the same bin use different banks) and are
-// flushed into uint64 global counts.
+// inside one row of cells) and walks the neighbour cells of Sec. 3.3 as
+// contiguous spans of the other catalog. The spans are cut into chunks of 64
+// neighbour points, one per lane in VGPRs; the home points are wave-uniform
+// and arrive four at a time through scalar loads, so that each lane evaluates
+// four independent pairs per step. Counts go to one 64-bit LDS histogram per
+// workgroup (several interleaved copies, so that lanes hitting the same bin
+// use different banks), summed into uint64 global counts at the end.
 //
 // Precision paths
 //  - FP64: every pair is classified by the canonical FP64 predicates.
@@ -17,889 +17,11 @@
 //    queue that is drained 64 pairs at a time through the canonical FP64
 //    predicates, so the counts equal the FP64 ones.
 //  - FP32_ONLY: FP32 decisions only.
-#include <math.h>
-#include <stdint.h>
-
-#include "cute_internal.h"
-#include "runtime.h"
+#include "count_device.h"
 
 namespace cute {
 
 namespace {
-
-constexpr int kQCap = 128;             // retest queue entries per wave
-constexpr uint32_t kNoBin = 0xffffffffu;
-constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr uint32_t kTileMax = 64;      // home points per tile
-constexpr uint32_t kSpanCap = 192;     // neighbour spans buffered per wave
-
-// Read-only device memory seen through the constant address space: loads at
-// wave-uniform addresses become scalar (s_load) loads into SGPRs.
-typedef const __attribute__((address_space(4))) float* cfp;
-typedef const __attribute__((address_space(4))) double* cdp;
-typedef const __attribute__((address_space(4))) uint32_t* cu32p;
-
-__device__ __forceinline__ float4 load_u32x4f(const float4* p, uint32_t j) {
-    const cfp f = (cfp)(const void*)p;
-    return make_float4(f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3]);
-}
-__device__ __forceinline__ P64 load_u64x3(const P64* p, uint32_t j) {
-    const cdp f = (cdp)(const void*)p;
-    P64 q;
-    q.x = f[4 * j];
-    q.y = f[4 * j + 1];
-    q.z = f[4 * j + 2];
-    q.w = 0.0;
-    return q;
-}
-
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int unii(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
-
-// ---------------------------------------------------------------------------
-// Canonical FP64 classification (identical predicates to a plain FP64 double
-// loop: squared quantities against squared edges, explicit fused multiply-adds,
-// no square root or division). dx, dy, dz are the separation p - q (minimum
-// image already applied), l the sum p + q (midpoint line of sight).
-// Returns the flattened bin or kNoBin.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int last_le64(const double* t, int n, double v, int k) {
-    // largest k in [0, n-1] with t[k] <= v, given t[0] <= v < t[n]; k is a guess
-    while (k > 0 && v < t[k]) k--;
-    while (k < n - 1 && v >= t[k + 1]) k++;
-    return k;
-}
-
-__device__ __forceinline__ int last_ratio64(const double* t, int n, double num, double den,
-                                            int k) {
-    // largest k in [0, n-1] with num >= t[k] * den, given it holds at 0
-    while (k > 0 && !(num >= t[k] * den)) k--;
-    while (k < n - 1 && num >= t[k + 1] * den) k++;
-    return k;
-}
-
-template <int MODE>
-__device__ __forceinline__ uint32_t classify64(const CountArgs& P, const double* T1,
-                                               const double* T2, double dx, double dy, double dz,
-                                               double lx, double ly, double lz, int k1g,
-                                               int k2g) {
-    const int n1 = P.n1, n2 = P.n2;
-    double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    if (MODE == M_MONO || MODE == M_THETA) {
-        if (!(T1[0] <= d2 && d2 < T1[n1])) return kNoBin;
-        return (uint32_t)last_le64(T1, n1, d2, k1g);
-    }
-    if (MODE == M_RMU_Z || MODE == M_RMU_MID) {
-        if (!(T1[0] <= d2 && d2 < T1[n1])) return kNoBin;
-        int ir = last_le64(T1, n1, d2, k1g);
-        double num, den;
-        if (MODE == M_RMU_Z) {
-            num = dz * dz;
-            den = d2;
-        } else {
-            double sl = fma(dz, lz, fma(dy, ly, dx * lx));
-            double ll = fma(lz, lz, fma(ly, ly, lx * lx));
-            if (ll == 0.0) {
-                num = 0.0;
-                den = 1.0;
-            } else {
-                num = sl * sl;
-                den = d2 * ll;
-            }
-        }
-        if (d2 == 0.0) {
-            num = 0.0;
-            den = 1.0;
-        }
-        if (!(num >= T2[0] * den)) return kNoBin;
-        if (!P.mu_top_closed && num >= T2[n2] * den) return kNoBin;
-        int im = last_ratio64(T2, n2, num, den, k2g);
-        return (uint32_t)(ir * n2 + im);
-    }
-    // SIGMAPI, midpoint line of sight
-    double sl = fma(dz, lz, fma(dy, ly, dx * lx));
-    double ll = fma(lz, lz, fma(ly, ly, lx * lx));
-    double cx = fma(dy, lz, -(dz * ly));
-    double cy = fma(dz, lx, -(dx * lz));
-    double cz = fma(dx, ly, -(dy * lx));
-    double c2 = fma(cz, cz, fma(cy, cy, cx * cx));
-    double sn, pn, den;
-    if (ll == 0.0) {
-        sn = d2;
-        pn = 0.0;
-        den = 1.0;
-    } else {
-        sn = c2;
-        pn = sl * sl;
-        den = ll;
-    }
-    if (!(sn >= T1[0] * den)) return kNoBin;
-    if (sn >= T1[n1] * den) return kNoBin;
-    if (!(pn >= T2[0] * den)) return kNoBin;
-    if (pn >= T2[n2] * den) return kNoBin;
-    int is = last_ratio64(T1, n1, sn, den, k1g);
-    int ip = last_ratio64(T2, n2, pn, den, k2g);
-    return (uint32_t)(is * n2 + ip);
-}
-
-// Guess of the dimension-1 bin from a float value (used to start the exact
-// search; any guess in range gives the right answer).
-template <int MODE, int EST>
-__device__ __forceinline__ int guess1(const CountArgs& P, float v) {
-    float t;
-    if (MODE == M_THETA) {
-        float c = __builtin_amdgcn_sqrtf(v);
-        float th = fmaf(c * v, 1.0f / 24.0f, c);  // 2 asin(c/2) to third order
-        t = (EST == E_LOG) ? __builtin_amdgcn_logf(th) : th;
-    } else {
-        t = (EST == E_LOG) ? __builtin_amdgcn_logf(v) : __builtin_amdgcn_sqrtf(v);
-    }
-    return (int)__builtin_amdgcn_fmed3f(fmaf(t, P.e1a, P.e1b), 0.0f, P.n1m1);
-}
-
-// clamp to [0, n-1] with one v_med3; a NaN estimate converts to bin 0 or is
-// clamped, so the index always stays in range
-__device__ __forceinline__ int guess_lin(float t, float a, float b, float nm1) {
-    return (int)__builtin_amdgcn_fmed3f(fmaf(t, a, b), 0.0f, nm1);
-}
-
-// Canonical classification of a queued pair from the sorted FP64 copies.
-template <int MODE, int EST>
-__device__ uint32_t classify_pair64(const CountArgs& P, const double* T1, const double* T2,
-                                    const P64& p, const P64& q) {
-    double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-    if (P.periodic) {
-        const double L = P.L, h = 0.5 * P.L;
-        dx = dx > h ? dx - L : (dx < -h ? dx + L : dx);
-        dy = dy > h ? dy - L : (dy < -h ? dy + L : dy);
-        dz = dz > h ? dz - L : (dz < -h ? dz + L : dz);
-    }
-    double lx = p.x + q.x, ly = p.y + q.y, lz = p.z + q.z;
-    double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    float v = (float)d2;
-    int k1, k2 = 0;
-    if (MODE == M_SIGMAPI) {
-        double sl = fma(dz, lz, fma(dy, ly, dx * lx));
-        double ll = fma(lz, lz, fma(ly, ly, lx * lx));
-        float inv = ll > 0.0 ? (float)(1.0 / ll) : 0.0f;
-        float pi2 = (float)(sl * sl) * inv;
-        float sg2 = fmaxf(v - pi2, 0.0f);
-        k1 = guess_lin(__builtin_amdgcn_sqrtf(sg2), P.e1a, P.e1b, P.n1m1);
-        k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2m1);
-    } else {
-        k1 = guess1<MODE, EST>(P, v);
-        if (MODE == M_RMU_Z) {
-            float mu = d2 > 0.0 ? (float)(fabs(dz) / sqrt(d2)) : 0.0f;
-            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
-        } else if (MODE == M_RMU_MID) {
-            double sl = fma(dz, lz, fma(dy, ly, dx * lx));
-            double ll = fma(lz, lz, fma(ly, ly, lx * lx));
-            float mu = (d2 > 0.0 && ll > 0.0) ? (float)(fabs(sl) / sqrt(d2 * ll)) : 0.0f;
-            k2 = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
-        }
-    }
-    return classify64<MODE>(P, T1, T2, dx, dy, dz, lx, ly, lz, k1, k2);
-}
-
-// ---------------------------------------------------------------------------
-// FP32 classification with rounding bands.
-// Output: in   -> certainly in bin *bin (same as the canonical decision)
-//         out  -> certainly not counted
-//         else -> ambiguous (to be re-tested); *bin holds the FP32 guess
-// tent: the FP32-only decision (bin or kNoBin), used by FP32_ONLY and for
-//       counting flips.
-// ---------------------------------------------------------------------------
-struct C32 {
-    bool in, out;
-    uint32_t bin;
-};
-
-template <int MODE, int EST, bool WANT_TENT>
-__device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
-                                          const float2* B2, float dx, float dy, float dz,
-                                          float lx, float ly, float lz, uint32_t* tent,
-                                          float dA0v) {
-    C32 c;
-    float v = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    if (MODE == M_MONO | MODE == M_THETA) {
-        int k = guess1<MODE, EST>(P, v);
-        float2 b = B1[k];
-        c.in = (v >= b.x) & (v < b.y);
-        c.out = (v >= P.out_hi) | (v < P.out_lo);
-        c.bin = (uint32_t)k;
-        if (WANT_TENT) *tent = (v >= P.bot32 & v < P.top32) ? (uint32_t)k : kNoBin;
-        return c;
-    }
-    if (MODE == M_RMU_Z) {
-        float rinv = __builtin_amdgcn_rsqf(v);
-        float r = v * rinv;
-        int k;
-        if (EST == E_LOG) {
-            k = guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1m1);
-        } else {
-            k = guess_lin(r, P.e1a, P.e1b, P.n1m1);
-        }
-        float mu = fabsf(dz) * rinv;
-        int km = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
-        float dz2 = dz * dz;
-        float2 b = B1[k];
-        float2 m = B2[km];
-        // the v term of the band is folded into the r term on the host
-        // (v <= r_max r wherever the mu decision matters)
-        float delta = fmaf(P.dA1, r, dA0v);
-        float flo = fmaf(m.x, v, dz2);
-        float fhi = fmaf(m.y, v, dz2);
-        bool rin = (v >= b.x) & (v < b.y);
-        bool min_ = (flo >= delta) & (fhi <= -delta);
-        c.in = rin & min_;
-        // only r decides a clean "out"; a pair outside a partial mu range is
-        // re-tested instead (never the case for mu in [0, 1])
-        c.out = (v >= P.out_hi) | (v < P.out_lo);
-        c.bin = __umul24((uint32_t)k, (uint32_t)P.n2) + (uint32_t)km;
-        if (WANT_TENT) {
-            bool rr = v >= P.bot32 & v < P.top32;
-            bool mm = true;
-            if (P.d2_partial) mm = (fmaf(P.nlo2_first, v, dz2) >= 0.0f) & (fmaf(P.nhi2_last, v, dz2) < 0.0f);
-            *tent = (rr & mm) ? c.bin : kNoBin;
-        }
-        return c;
-    }
-    if (MODE == M_RMU_MID) {
-        float sl = fmaf(dz, lz, fmaf(dy, ly, dx * lx));
-        float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
-        float rinv = __builtin_amdgcn_rsqf(v);
-        float r = v * rinv;
-        int k = (EST == E_LOG) ? guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1m1)
-                               : guess_lin(r, P.e1a, P.e1b, P.n1m1);
-        float w = v * ll;
-        float sl2 = sl * sl;
-        float lnorm = __builtin_amdgcn_sqrtf(ll);
-        float mu = fabsf(sl) * rinv * __builtin_amdgcn_rcpf(lnorm);
-        int km = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
-        float2 b = B1[k];
-        float2 m = B2[km];
-        float delta = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, r, P.dA0)),
-                           fmaf(lnorm, fmaf(P.dB2, v, fmaf(P.dB1, r, P.dB0)),
-                                fmaf(P.dC2, v, P.dC0)));
-        float flo = fmaf(m.x, w, sl2);
-        float fhi = fmaf(m.y, w, sl2);
-        bool rin = (v >= b.x) & (v < b.y);
-        bool min_ = (flo >= delta) & (fhi <= -delta);
-        c.in = rin & min_;
-        c.out = (v >= P.out_hi) | (v < P.out_lo);
-        c.bin = __umul24((uint32_t)k, (uint32_t)P.n2) + (uint32_t)km;
-        if (WANT_TENT) {
-            bool rr = v >= P.bot32 & v < P.top32;
-            bool mm = true;
-            if (P.d2_partial) mm = (fmaf(P.nlo2_first, w, sl2) >= 0.0f) & (fmaf(P.nhi2_last, w, sl2) < 0.0f);
-            *tent = (rr & mm) ? c.bin : kNoBin;
-        }
-        return c;
-    }
-    // SIGMAPI (midpoint): sigma^2 ll = |s|^2 |l|^2 - (s.l)^2, pi^2 ll = (s.l)^2
-    float sl = fmaf(dz, lz, fmaf(dy, ly, dx * lx));
-    float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
-    float sl2 = sl * sl;
-    float c2 = fmaf(v, ll, -sl2);
-    float rll = __builtin_amdgcn_rcpf(ll);
-    float sg = __builtin_amdgcn_sqrtf(fmaxf(c2 * rll, 0.0f));
-    float pp = __builtin_amdgcn_sqrtf(sl2 * rll);
-    int ks = guess_lin(sg, P.e1a, P.e1b, P.n1m1);
-    int kp = guess_lin(pp, P.e2a, P.e2b, P.n2m1);
-    float t = __builtin_amdgcn_sqrtf(v);
-    float lnorm = __builtin_amdgcn_sqrtf(ll);
-    float ds = fmaf(ll, fmaf(P.sA2, v, fmaf(P.sA1, t, P.sA0)),
-                    fmaf(lnorm, fmaf(P.sB2, v, fmaf(P.sB1, t, P.sB0)), fmaf(P.sC2, v, P.sC0)));
-    float dp = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, t, P.dA0)),
-                    fmaf(lnorm, fmaf(P.dB2, v, fmaf(P.dB1, t, P.dB0)), fmaf(P.dC2, v, P.dC0)));
-    float2 bs = B1[ks];
-    float2 bp = B2[kp];
-    float fslo = fmaf(bs.x, ll, c2), fshi = fmaf(bs.y, ll, c2);
-    float fplo = fmaf(bp.x, ll, sl2), fphi = fmaf(bp.y, ll, sl2);
-    c.in = (fslo >= ds) & (fshi <= -ds) & (fplo >= dp) & (fphi <= -dp);
-    // out of range: sigma >= sigma_max, pi >= pi_max, or below the first edges
-    float fstop = fmaf(P.out_hi, ll, c2);       // out_hi holds -S2f[n1]
-    float fptop = fmaf(P.nhi2_last, ll, sl2);   // -P2f[n2]
-    float fsbot = fmaf(P.out_lo, ll, c2);       // out_lo holds -S2f[0] (or +BIG)
-    float fpbot = fmaf(P.nlo2_first, ll, sl2);  // -P2f[0] (or +BIG)
-    c.out = (fstop >= ds) | (fptop >= dp) | (fsbot <= -ds) | (fpbot <= -dp);
-    c.bin = __umul24((uint32_t)ks, (uint32_t)P.n2) + (uint32_t)kp;
-    if (WANT_TENT) {
-        bool ok = (fsbot >= 0.0f) & (fstop < 0.0f) & (fpbot >= 0.0f) & (fptop < 0.0f);
-        *tent = ok ? c.bin : kNoBin;
-    }
-    return c;
-}
-
-// ---------------------------------------------------------------------------
-// Per-wave working state.
-// ---------------------------------------------------------------------------
-// Periodic image of a neighbour point: (kx+1) | (ky+1) << 2 | (kz+1) << 4,
-// k in {-1, 0, 1}; the image lies at q + k L in the home point's frame.
-constexpr uint32_t kNoShift = 0x15u;
-
-__device__ __forceinline__ float shift32(uint32_t code, int axis, float Lf) {
-    return (float)((int)((code >> (2 * axis)) & 3u) - 1) * Lf;
-}
-__device__ __forceinline__ double shift64(uint32_t code, int axis, double L) {
-    return (double)((int)((code >> (2 * axis)) & 3u) - 1) * L;
-}
-
-// Per-wave state. The queue, the histogram and the re-test statistics live
-// in LDS; the rare paths below are real (non-inlined) calls that take the
-// queue length by value and return it, so the hot loop keeps few registers.
-struct WaveState {
-    unsigned long long* hist;  // the workgroup's shared 64-bit histogram (hist_words)
-    uint32_t* qi;        // re-test queue: home index
-    uint32_t* qj;        // re-test queue: neighbour index
-    uint32_t* qc;        // re-test queue: neighbour image code
-    unsigned long long* rstat;  // [0] retests, [1] flips (LDS)
-    uint32_t tail;       // queued entries (wave-uniform)
-    uint64_t evals, tiles;
-};
-
-// The workgroup's histogram: 64-bit LDS counters (no overflow, so no
-// flushing before the end of the kernel), several interleaved copies so that
-// lanes hitting the same bin use different banks. copies is a power of two:
-// word = (bin << log2(copies)) | (lane & (copies - 1)).
-__device__ __forceinline__ void hist_add(unsigned long long* hist, uint32_t bin, int copies,
-                                         int lane) {
-    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
-    atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], 1ull);
-}
-
-// The same increment with the lane's copy folded into its base pointer.
-__device__ __forceinline__ void hist_add_lane(unsigned long long* lhist, uint32_t bin, uint32_t lc) {
-    atomicAdd(&lhist[bin << lc], 1ull);
-}
-
-// Re-test up to 64 queued pairs per pass, one per lane, through the canonical
-// FP64 predicates; count the pairs whose FP32-only decision differs (flips).
-// Returns the new queue length.
-template <int MODE, int EST>
-__device__ __attribute__((noinline)) uint32_t drain_queue(
-    const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
-    unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
-    const double* T2, int lane, uint32_t tail, bool all) {
-    const CountArgs& P = *Pg;
-    tail = uni(tail);
-    while (tail >= 64u || (all && tail > 0u)) {
-        const uint32_t n = tail < 64u ? tail : 64u;
-        const bool act = (uint32_t)lane < n;
-        uint32_t k = kNoBin, t = kNoBin;
-        if (act) {
-            const uint32_t i = qi[lane], j = qj[lane], code = qc[lane];
-            const P64 p = P.A.p64[i];
-            const P64 q = P.B.p64[j];
-            k = classify_pair64<MODE, EST>(P, T1, T2, p, q);
-            if (k != kNoBin) hist_add(hist, k, P.copies, lane);
-            // the FP32-only decision of the same pair, as the main loop made it
-            const float4 a = P.A.p32[i];
-            const float4 b = P.B.p32[j];
-            const float Lf = (float)P.L;
-            const float qx = b.x - (P.offx - shift32(code, 0, Lf));
-            const float qy = b.y - (P.offy - shift32(code, 1, Lf));
-            const float qz = b.z - (P.offz - shift32(code, 2, Lf));
-            (void)classify32<MODE, EST, true>(P, B1, B2, a.x - qx, a.y - qy, a.z - qz,
-                                              a.x + (qx + P.lcx), a.y + (qy + P.lcy),
-                                              a.z + (qz + P.lcz), &t, P.dA0);
-        }
-        const uint64_t fl = __builtin_amdgcn_ballot_w64(act && k != t);
-        if (lane == 0) {
-            rstat[0] += n;
-            rstat[1] += (unsigned long long)__popcll(fl);
-        }
-        const uint32_t rest = tail - n;
-        if ((uint32_t)lane < rest) {
-            const uint32_t a = qi[n + lane], b = qj[n + lane], c = qc[n + lane];
-            qi[lane] = a;
-            qj[lane] = b;
-            qc[lane] = c;
-        }
-        tail = rest;
-    }
-    return tail;
-}
-
-// Queue the lanes set in m[u] (pair: home h + u, this lane's neighbour).
-template <int MODE, int EST, uint32_t U>
-__device__ __attribute__((noinline)) uint32_t enqueue(
-    const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
-    unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
-    const double* T2, int lane, uint32_t tail, uint32_t h, uint32_t lj, uint32_t lcode,
-    uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3) {
-    tail = uni(tail);
-    for (uint32_t u = 0; u < U; u++) {
-        const uint64_t m = u == 0 ? m0 : (u == 1 ? m1 : (u == 2 ? m2 : m3));
-        if (m == 0) continue;
-        const uint32_t pre =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if ((m >> lane) & 1ull) {
-            const uint32_t pos = tail + pre;
-            qi[pos] = h + u;
-            qj[pos] = lj;
-            qc[pos] = lcode;
-        }
-        tail += (uint32_t)__popcll(m);
-        if (tail >= 64u)
-            tail = drain_queue<MODE, EST>(Pg, hist, qi, qj, qc, rstat, B1, B2, T1, T2, lane, tail,
-                                          false);
-    }
-    return tail;
-}
-
-// ---------------------------------------------------------------------------
-// The hot loop. A chunk holds up to 64 neighbour points, one per lane, in
-// VGPRs; the home points of the tile are wave-uniform and arrive through
-// scalar loads, U at a time, so that U independent pair evaluations per lane
-// interleave. Every lane evaluates the pair (home h, its neighbour).
-// ---------------------------------------------------------------------------
-template <int MODE, int PREC, int EST, bool MASKED, uint32_t U>
-__device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const float2* B1,
-                                       const float2* B2, const double* T1, const double* T2,
-                                       int lane, bool lvalid, bool lmask, uint32_t lj,
-                                       uint32_t lcode, float qx, float qy, float qz, float qlx,
-                                       float qly, float qlz, float dA0v, uint32_t h) {
-    float hx[U], hy[U], hz[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++) {
-        const float4 p = load_u32x4f(P.A.p32, h + u);
-        hx[u] = p.x;
-        hy[u] = p.y;
-        hz[u] = p.z;
-    }
-    uint32_t bin[U];
-    bool cnt[U], amb[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++) {
-        const bool act = lvalid & (!MASKED | !lmask | (lj > h + u));
-        const float dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
-        float lx = 0.f, ly = 0.f, lz = 0.f;
-        if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-            lx = hx[u] + qlx;
-            ly = hy[u] + qly;
-            lz = hz[u] + qlz;
-        }
-        if (PREC == P_FP32O) {
-            uint32_t tent;
-            (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent, dA0v);
-            cnt[u] = act & (tent != kNoBin);
-            bin[u] = tent;
-            amb[u] = false;
-        } else {
-            const C32 c =
-                classify32<MODE, EST, false>(P, B1, B2, dx, dy, dz, lx, ly, lz, nullptr, dA0v);
-            cnt[u] = act & c.in;
-            amb[u] = act & !(c.in | c.out);
-            bin[u] = c.bin;
-        }
-    }
-    // one vote for the whole step; the per-pair votes only on the rare path
-    uint64_t any_amb = 0;
-    if (PREC == P_FP32E) {
-        bool any = false;
-#pragma unroll
-        for (uint32_t u = 0; u < U; u++) any = any | amb[u];
-        any_amb = __builtin_amdgcn_ballot_w64(any);
-    }
-    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)P.copies);
-    unsigned long long* lhist = W.hist + (lane & (P.copies - 1));
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add_lane(lhist, bin[u], lc);
-    if (PREC == P_FP32E && any_amb) {
-        uint64_t m[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (uint32_t u = 0; u < U; u++) m[u] = __builtin_amdgcn_ballot_w64(amb[u]);
-        W.tail = enqueue<MODE, EST, U>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,
-                                       W.tail, h, lj, lcode, m[0], m[1], m[2], m[3]);
-    }
-}
-
-template <int MODE, int EST, bool MASKED, bool SHIFTED, uint32_t U>
-__device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const double* T1,
-                                       const double* T2, int lane, bool lvalid, bool lmask,
-                                       uint32_t lj, double qx, double qy, double qz, double sx, double sy,
-                                       double sz, uint32_t h) {
-    double hx[U], hy[U], hz[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++) {
-        const P64 p = load_u64x3(P.A.p64, h + u);
-        hx[u] = p.x;
-        hy[u] = p.y;
-        hz[u] = p.z;
-    }
-    uint32_t bin[U];
-    bool cnt[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++) {
-        const bool act = lvalid & (!MASKED | !lmask | (lj > h + u));
-        double dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
-        if (SHIFTED) {
-            // the neighbour's periodic image: equal to the minimum-image wrap
-            // for every pair the stencil can form
-            dx = dx - sx;
-            dy = dy - sy;
-            dz = dz - sz;
-        }
-        double lx = 0.0, ly = 0.0, lz = 0.0;
-        if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
-            lx = hx[u] + qx;
-            ly = hy[u] + qy;
-            lz = hz[u] + qz;
-        }
-        int k1 = 0, k2 = 0;
-        const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const float v = (float)d2;
-        if (MODE == M_MONO || MODE == M_THETA) {
-            k1 = guess1<MODE, EST>(P, v);
-        } else if (MODE == M_RMU_Z) {
-            k1 = guess1<M_MONO, EST>(P, v);
-            k2 = guess_lin(fabsf((float)dz) * __builtin_amdgcn_rsqf(v), P.e2a, P.e2b, P.n2m1);
-        } else if (MODE == M_RMU_MID) {
-            k1 = guess1<M_MONO, EST>(P, v);
-            const float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
-            const float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
-            k2 = guess_lin(fabsf(sl) * __builtin_amdgcn_rsqf(v * ll), P.e2a, P.e2b, P.n2m1);
-        } else {
-            const float sl = (float)fma(dz, lz, fma(dy, ly, dx * lx));
-            const float ll = (float)fma(lz, lz, fma(ly, ly, lx * lx));
-            const float pi2 = sl * sl * __builtin_amdgcn_rcpf(ll);
-            k1 = guess_lin(__builtin_amdgcn_sqrtf(fmaxf(v - pi2, 0.0f)), P.e1a, P.e1b, P.n1m1);
-            k2 = guess_lin(__builtin_amdgcn_sqrtf(pi2), P.e2a, P.e2b, P.n2m1);
-        }
-        bin[u] = classify64<MODE>(P, T1, T2, dx, dy, dz, lx, ly, lz, k1, k2);
-        cnt[u] = act & (bin[u] != kNoBin);
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane);
-}
-
-// The chunk being assembled from neighbour spans (per-lane fields in VGPRs,
-// the rest wave-uniform).
-struct Chunk {
-    uint32_t filled;   // lanes holding a neighbour
-    bool masked;       // some lane needs the j > i test
-    bool shifted;      // some lane holds a periodic image
-    uint32_t lj;       // per lane: neighbour index
-    uint32_t lcode;    // per lane: image code
-    bool lmask;        // per lane: j > i test applies
-};
-
-template <int MODE, int PREC, int EST>
-__device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
-                          const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
-                          uint32_t te) {
-    constexpr uint32_t U = 4;
-    const uint32_t nh = te - ts;
-    const bool lvalid = (uint32_t)lane < C.filled;
-    if (PREC == P_FP64) {
-        double qx = 0.0, qy = 0.0, qz = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        if (lvalid) {
-            const P64 q = P.B.p64[C.lj];
-            qx = q.x;
-            qy = q.y;
-            qz = q.z;
-            sx = shift64(C.lcode, 0, P.L);
-            sy = shift64(C.lcode, 1, P.L);
-            sz = shift64(C.lcode, 2, P.L);
-        }
-#define CUTE_RUN64(MSK, SH)                                                                     \
-    {                                                                                           \
-        uint32_t h = ts;                                                                        \
-        for (; h + U <= te; h += U)                                                             \
-            step64<MODE, EST, MSK, SH, U>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
-                                          sx, sy, sz, h);                                       \
-        for (; h < te; h++)                                                                     \
-            step64<MODE, EST, MSK, SH, 1>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
-                                          sx, sy, sz, h);                                       \
-    }
-        if (C.masked) {
-            if (C.shifted) CUTE_RUN64(true, true) else CUTE_RUN64(true, false)
-        } else {
-            if (C.shifted) CUTE_RUN64(false, true) else CUTE_RUN64(false, false)
-        }
-#undef CUTE_RUN64
-    } else {
-        // a band constant kept in a VGPR (an fma can read only one SGPR)
-        float dA0v;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(dA0v) : "s"(P.dA0));
-        // the neighbour in the home grid's FP32 frame: q - (cA - cB) for two
-        // open grids, or its periodic image q + k L (only one of the two is
-        // ever non-zero), and q + 2 cA for the midpoint line of sight
-        float qx = 0.f, qy = 0.f, qz = 0.f, qlx = 0.f, qly = 0.f, qlz = 0.f;
-        if (lvalid) {
-            const float4 q = P.B.p32[C.lj];
-            const float Lf = (float)P.L;
-            qx = q.x - (P.offx - shift32(C.lcode, 0, Lf));
-            qy = q.y - (P.offy - shift32(C.lcode, 1, Lf));
-            qz = q.z - (P.offz - shift32(C.lcode, 2, Lf));
-            qlx = qx + P.lcx;
-            qly = qy + P.lcy;
-            qlz = qz + P.lcz;
-        }
-#define CUTE_RUN32(MSK)                                                                            \
-    {                                                                                              \
-        uint32_t h = ts;                                                                           \
-        for (; h + U <= te; h += U)                                                                \
-            step32<MODE, PREC, EST, MSK, U>(P, W, B1, B2, T1, T2, lane, lvalid, C.lmask, C.lj,     \
-                                            C.lcode, qx, qy, qz, qlx, qly, qlz, dA0v, h);          \
-        for (; h < te; h++)                                                                        \
-            step32<MODE, PREC, EST, MSK, 1>(P, W, B1, B2, T1, T2, lane, lvalid, C.lmask, C.lj,     \
-                                            C.lcode, qx, qy, qz, qlx, qly, qlz, dA0v, h);          \
-    }
-        if (C.masked) CUTE_RUN32(true) else CUTE_RUN32(false)
-#undef CUTE_RUN32
-    }
-    C.filled = 0;
-    C.masked = false;
-    C.shifted = false;
-}
-
-// Append the neighbour span [a0, a1) (image code, j > i test) to the chunk,
-// running every chunk that fills up.
-template <int MODE, int PREC, int EST>
-__device__ void feed(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
-                     const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
-                     uint32_t te, uint32_t a0, uint32_t a1, uint32_t code, bool masked) {
-    if (masked && a1 > a0) {
-        // lanes with neighbour j pair with the home points h < j: sum of (j - ts)
-        const uint64_t lo_ = a0 - ts, hi_ = a1 - 1u - ts;
-        W.evals += (lo_ + hi_) * (hi_ - lo_ + 1u) / 2u;
-    } else if (a1 > a0) {
-        W.evals += (uint64_t)(te - ts) * (a1 - a0);
-    }
-    while (a0 < a1) {
-        const uint32_t room = 64u - C.filled;
-        const uint32_t take = (a1 - a0) < room ? (a1 - a0) : room;
-        const uint32_t l = (uint32_t)lane;
-        if (l >= C.filled && l < C.filled + take) {
-            C.lj = a0 + (l - C.filled);
-            C.lcode = code;
-            C.lmask = masked;
-        }
-        C.filled += take;
-        C.masked = C.masked | masked;
-        C.shifted = C.shifted | (code != kNoShift);
-        a0 += take;
-        if (C.filled == 64u) run_chunk<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, C, ts, te);
-    }
-}
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-__device__ __forceinline__ int imod(int a, int n) {
-    int r = a % n;
-    return r < 0 ? r + n : r;
-}
-
-// Span list of one tile, built in LDS before any pair is evaluated, so that
-// the stencil's FP64 temporaries are dead while the hot loop runs.
-struct SpanBuf {
-    uint32_t* a;   // first neighbour index
-    uint32_t* b;   // one past the last
-    uint32_t* f;   // image code (low 8 bits) | j > i test (bit 8)
-    uint32_t n;    // entries (wave-uniform)
-};
-
-__device__ __forceinline__ void push_span(SpanBuf& S, int lane, uint32_t a0, uint32_t a1,
-                                          uint32_t code, bool masked) {
-    if (a1 <= a0) return;
-    if (lane == 0) {
-        S.a[S.n] = a0;
-        S.b[S.n] = a1;
-        S.f[S.n] = code | (masked ? 0x100u : 0u);
-    }
-    S.n++;
-}
-
-// Neighbour spans of the cell range [pa, pb] of row rb in the B grid. In the
-// home row of an autocorrelation the range starting at the tile's first cell
-// is split into the tile itself (pairs j > i only) and the rest.
-__device__ __forceinline__ void push_cells(SpanBuf& S, int lane, const cu32p cs, uint32_t rb,
-                                           int pa, int pb, uint32_t code, bool home_start,
-                                           uint32_t ts, uint32_t te) {
-    const uint32_t j0 = uni(cs[rb + (uint32_t)pa]);
-    const uint32_t j1 = uni(cs[rb + (uint32_t)pb + 1u]);
-    if (home_start) {
-        // points of the first cell before the tile pair with it from their own tile
-        const uint32_t m1 = te < j1 ? te : j1;
-        push_span(S, lane, ts, m1, code, true);
-        push_span(S, lane, m1 > te ? m1 : te, j1, code, false);
-    } else {
-        push_span(S, lane, j0, j1, code, false);
-    }
-}
-
-// Fill the span buffer with the neighbour spans of rows [*row, ...) of the
-// tile's stencil (Sec. 3.3: the cells within r_max of the tile), stopping
-// before the buffer could overflow. Returns true when every row is done.
-__device__ bool gen_spans(const CountArgs& P, const Tile& tl, int lane, SpanBuf& S, int* row) {
-    const uint32_t ts = tl.start, te = tl.end;
-    const int c0 = (int)(tl.c0c1 & 0xffffu), c1 = (int)(tl.c0c1 >> 16);
-    const GridView& A = P.A;
-    const GridView& B = P.B;
-    const int cy = (int)(tl.row % (uint32_t)A.ny), cz = (int)(tl.row / (uint32_t)A.ny);
-    const cu32p cs = (cu32p)(const void*)B.cstart;
-    S.n = 0;
-    const uint32_t room = kSpanCap - 3;
-
-    if (P.geom == CUTE_GEOM_SPHERE) {
-        // tile pixel block: phi in [c0, c1+1) * ax, cos theta in one band
-        const double zlo = A.oy + cy * A.ay, zhi = zlo + A.ay;
-        const double zl = fmax(-1.0, fmin(1.0, zlo)), zh = fmax(-1.0, fmin(1.0, zhi));
-        const double th_lo = acos(zh), th_hi = acos(zl);
-        const double ths = P.th_s;
-        const double zn_hi = (th_lo - ths <= 0.0) ? 1.0 : cos(th_lo - ths);
-        const double zn_lo = (th_hi + ths >= kPi) ? -1.0 : cos(th_hi + ths);
-        int b0 = (int)floor((zn_lo - B.oy) / B.ay) - 1, b1 = (int)floor((zn_hi - B.oy) / B.ay) + 1;
-        b0 = clampi(b0, 0, B.ny - 1);
-        b1 = clampi(b1, 0, B.ny - 1);
-        // half-width in phi of a cap of radius th_s around any tile point:
-        // asin(sin th_s / sin theta) at the tile colatitude nearest a pole
-        const double zmax2 = fmax(zl * zl, zh * zh);
-        const double smin = sqrt(fmax(0.0, 1.0 - zmax2));
-        bool full = !(P.sin_th_s < smin * (1.0 - 1e-9)) || (P.th_s >= 0.5 * kPi);
-        const double hw = full ? 0.0 : asin(P.sin_th_s / smin) * (1.0 + 1e-9) + 1e-12;
-        const double phlo = c0 * A.ax - hw, phhi = (c1 + 1) * A.ax + hw;
-        const int x0 = (int)floor(phlo / B.ax) - 1, x1 = (int)floor(phhi / B.ax) + 1;
-        if (x1 - x0 + 1 >= B.nx) full = true;
-        for (int by = b0 + *row; by <= b1; by++) {
-            if (S.n > room) {
-                *row = by - b0;
-                return false;
-            }
-            const int byu = unii(by);
-            const bool same = P.is_auto && byu == cy;
-            if (P.is_auto && byu < cy) continue;
-            const uint32_t rb = (uint32_t)byu * (uint32_t)B.nx;
-            if (same) {
-                // index rule inside the home band: partners with a larger
-                // index, i.e. cells >= c0 up to the right reach, plus the left
-                // reach that wraps past phi = 2 pi onto the band's last cells
-                int p0b = B.nx - 1, p1a = 0, p1b = -1;
-                if (!full) {
-                    const int r1 = x1 < B.nx - 1 ? x1 : B.nx - 1;
-                    const int s2 = x0 < 0 ? x0 + B.nx : B.nx;
-                    if (s2 > r1 + 1) {
-                        p0b = r1;
-                        p1a = s2;
-                        p1b = B.nx - 1;
-                    }
-                }
-                push_cells(S, lane, cs, rb, c0, p0b, kNoShift, true, ts, te);
-                if (p1b >= p1a) push_cells(S, lane, cs, rb, p1a, p1b, kNoShift, false, ts, te);
-            } else if (full) {
-                push_cells(S, lane, cs, rb, 0, B.nx - 1, kNoShift, false, ts, te);
-            } else {
-                // cyclic range [x0, x1] (length < nx) split at the phi wrap
-                const int a0 = imod(x0, B.nx);
-                const int len = x1 - x0 + 1;
-                if (a0 + len <= B.nx) {
-                    push_cells(S, lane, cs, rb, a0, a0 + len - 1, kNoShift, false, ts, te);
-                } else {
-                    push_cells(S, lane, cs, rb, a0, B.nx - 1, kNoShift, false, ts, te);
-                    push_cells(S, lane, cs, rb, 0, a0 + len - 1 - B.nx, kNoShift, false, ts, te);
-                }
-            }
-        }
-        return true;
-    }
-
-    // 3-D boxes: the tile box, grown by R, selects rows of neighbour cells
-    const double R = P.Rs;
-    const double xlo = A.ox + c0 * A.ax, xhi = A.ox + (c1 + 1) * A.ax;
-    const double ylo = A.oy + cy * A.ay, yhi = ylo + A.ay;
-    const double zlo = A.oz + cz * A.az, zhi = zlo + A.az;
-    int y0 = (int)floor((ylo - R - B.oy) / B.ay), y1 = (int)floor((yhi + R - B.oy) / B.ay);
-    int z0 = (int)floor((zlo - R - B.oz) / B.az), z1 = (int)floor((zhi + R - B.oz) / B.az);
-    if (!P.periodic) {
-        y0 = clampi(y0, 0, B.ny - 1);
-        y1 = clampi(y1, 0, B.ny - 1);
-        z0 = clampi(z0, 0, B.nz - 1);
-        z1 = clampi(z1, 0, B.nz - 1);
-    }
-    const int nyr = y1 - y0 + 1;
-    const int nrows = nyr * (z1 - z0 + 1);
-    const double R2 = R * R;
-    for (int r = *row; r < nrows; r++) {
-        if (S.n > room) {
-            *row = r;
-            return false;
-        }
-        const int bzu = unii(z0 + r / nyr), byu = unii(y0 + r % nyr);
-        bool same = false;
-        if (P.is_auto) {
-            const int oz_ = bzu - cz, oy_ = byu - cy;
-            if (oz_ < 0 || (oz_ == 0 && oy_ < 0)) continue;
-            same = (oz_ == 0 && oy_ == 0);
-        }
-        // distance in y and z between the tile box and this row of cells
-        const double rylo = B.oy + byu * B.ay, ryhi = rylo + B.ay;
-        const double rzlo = B.oz + bzu * B.az, rzhi = rzlo + B.az;
-        const double dy = fmax(0.0, fmax(rylo - yhi, ylo - ryhi));
-        const double dz = fmax(0.0, fmax(rzlo - zhi, zlo - rzhi));
-        const double rem = R2 - dy * dy - dz * dz;
-        if (rem <= 0.0) continue;
-        const double w = sqrt(rem);
-        int x0 = (int)floor((xlo - w - B.ox) / B.ax), x1 = (int)floor((xhi + w - B.ox) / B.ax);
-        if (same && x0 < c0) x0 = c0;
-        int ry = byu, rz = bzu, ky = 0, kz = 0;
-        if (P.periodic) {
-            ky = floordiv(byu, B.ny);
-            kz = floordiv(bzu, B.nz);
-            ry = byu - ky * B.ny;
-            rz = bzu - kz * B.nz;
-        } else {
-            x0 = x0 < 0 ? 0 : x0;
-            x1 = x1 > B.nx - 1 ? B.nx - 1 : x1;
-            if (x0 > x1) continue;
-        }
-        const uint32_t rb = (uint32_t)B.nx * ((uint32_t)ry + (uint32_t)B.ny * (uint32_t)rz);
-        // split [x0, x1] at periodic wraps (at most two pieces)
-        int a0 = x0;
-        while (a0 <= x1) {
-            const int kx = P.periodic ? floordiv(a0, B.nx) : 0;
-            const int lim = P.periodic ? (kx + 1) * B.nx - 1 : x1;
-            const int a1 = x1 < lim ? x1 : lim;
-            const uint32_t code =
-                (uint32_t)(kx + 1) | ((uint32_t)(ky + 1) << 2) | ((uint32_t)(kz + 1) << 4);
-            push_cells(S, lane, cs, rb, a0 - kx * B.nx, a1 - kx * B.nx, code,
-                       same && kx == 0 && a0 == c0, ts, te);
-            a0 = a1 + 1;
-        }
-    }
-    return true;
-}
-
-// Count the pairs of one home tile: spans are generated into the LDS span
-// buffer, then fed chunk by chunk to the hot loop.
-template <int MODE, int PREC, int EST>
-__device__ void do_tile(const CountArgs& P, WaveState& W, SpanBuf& S, const float2* B1,
-                        const float2* B2, const double* T1, const double* T2, int lane,
-                        const Tile& tl) {
-    W.tiles++;
-    Chunk C;
-    C.filled = 0;
-    C.masked = false;
-    C.shifted = false;
-    C.lj = 0;
-    C.lcode = kNoShift;
-    C.lmask = false;
-    int row = 0;
-    bool done = false;
-    while (!done) {
-        done = gen_spans(P, tl, lane, S, &row);
-        for (uint32_t k = 0; k < S.n; k++) {
-            const uint32_t a0 = uni(S.a[k]), a1 = uni(S.b[k]), f = uni(S.f[k]);
-            feed<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end, a0, a1,
-                                  f & 0xffu, (f & 0x100u) != 0u);
-        }
-    }
-    if (C.filled) run_chunk<MODE, PREC, EST>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end);
-}
 
 // Four 4-wave workgroups per CU: the register budget stays at 128 VGPRs.
 template <int MODE, int PREC, int EST>
@@ -953,7 +75,7 @@ __global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
         tl.end = uni(tp[4 * t + 1]);
         tl.row = uni(tp[4 * t + 2]);
         tl.c0c1 = uni(tp[4 * t + 3]);
-        do_tile<MODE, PREC, EST>(P, W, S, B1, B2, T1, T2, lane, tl);
+        do_tile<MODE, PREC, EST, false>(P, W, S, B1, B2, T1, T2, lane, tl);
     }
     if (PREC == P_FP32E)
         W.tail = drain_queue<MODE, EST>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "cute.h"
 
@@ -12,8 +13,15 @@ namespace cute {
 
 // FP64 copy of a sorted point (the raw caller coordinates).
 struct alignas(32) P64 {
-    double x, y, z, w;
+    double x, y, z;
+    uint32_t idx;   // position of the point in the caller's input order
+    uint32_t pad;
 };
+
+// Sizes shared by the kernels and their launch planning.
+constexpr int kQCap = 128;        // FP64 re-test queue entries per wave
+constexpr int kSpanCap = 192;     // neighbour spans buffered per wave
+constexpr int kWgWaves = 4;       // waves per count workgroup
 
 // Kinds of pair classification the kernels are specialised for.
 enum Mode : int { M_MONO = 0, M_RMU_Z = 1, M_RMU_MID = 2, M_SIGMAPI = 3, M_THETA = 4 };
@@ -88,6 +96,24 @@ struct CountArgs {
     const double* T1;               // n1+1 canonical FP64 thresholds of dim 1
     const double* T2;               // n2+1 canonical FP64 thresholds of dim 2
     int mu_top_closed;              // last mu edge == 1
+    // point masks (batched counts): bit i of word i / 32 set = sorted point i
+    // excluded; nullptr = no mask
+    const uint32_t* mbA;
+    const uint32_t* mbB;
+};
+
+// A batched launch: the items (one CountArgs each, in device memory) share
+// the binning whose tables are given here.
+struct BatchArgs {
+    const CountArgs* items;
+    const uint32_t* chunks;         // per chunk: item, first tile, end tile, 0
+    uint32_t nchunks;
+    uint32_t* head;                 // next chunk to pop (global counter)
+    int n1, n2, nbins, copies, hist_words;
+    const double* T1;
+    const double* T2;
+    const float2* band1;
+    const float2* band2;
 };
 
 // Host-side grid object.
@@ -109,6 +135,46 @@ struct GridHost {
     GridView view() const;
 };
 
+// Inputs of the FP32 rounding-error bounds (absolute errors per component).
+struct ErrModel {
+    double ec = 0.0;     // FP32 separation components
+    double ec64 = 0.0;   // canonical FP64 separation components
+    double el = 0.0;     // FP32 line-of-sight components (midpoint)
+    double el64 = 0.0;   // FP64 line-of-sight components, before the sqrt(3) factor
+};
+
+// What one pair of grids contributes to a launch.
+struct ItemGeom {
+    GridView A, B;
+    int geom = 0, is_auto = 0, periodic = 0;
+    double L = 0.0, Rs = 0.0, th_s = 0.0, sin_th_s = 0.0;
+    float offx = 0.f, offy = 0.f, offz = 0.f, lcx = 0.f, lcy = 0.f, lcz = 0.f;
+    int max_w = 1;       // home-tile width limit in cells
+    ErrModel em;
+    double cost = 0.0;   // estimated candidate pairs
+};
+
+// A count launch: thresholds, band tables and the binning's kernel constants.
+struct Plan {
+    int mode = 0, est = 0;
+    double rmax = 0.0;               // largest countable separation
+    std::vector<double> T1, T2;      // canonical thresholds
+    std::vector<float2> band1, band2;
+    CountArgs a;
+    size_t lds = 0;                  // dynamic LDS bytes per workgroup
+};
+
+cute_status validate_binning(const cute_binning* b);
+bool same_binning(const cute_binning* a, const cute_binning* b);
+void plan_binning(const cute_binning* b, Plan& pl);
+cute_status plan_item(const GridHost& A, const GridHost& B, bool is_auto, const cute_binning* b,
+                      const Plan& pl, ItemGeom* g);
+ErrModel max_err(const ErrModel& x, const ErrModel& y);
+void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl);
+cute_status plan_lds(Plan& pl, size_t extra);
+void apply_item(const ItemGeom& g, CountArgs* a);
+cute_status hip_status(hipError_t e, const char* what);
+
 // error reporting
 void set_error(const std::string& msg);
 cute_status fail(cute_status s, const std::string& msg);
@@ -124,6 +190,14 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
 // persistent count launch; *grid_used receives the number of workgroups
 cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int wg_waves,
                          size_t lds_bytes, hipStream_t stream, int* grid_used);
+
+// batched counts: kernel attributes and occupancy (not capturable), the
+// launch itself (capturable), sorted-order mask bits, and a zero fill
+cute_status batch_prepare(int mode, int prec, int est, size_t lds, int* per_cu);
+cute_status batch_launch(const BatchArgs& ba, int mode, int prec, int est, int grid, size_t lds,
+                         hipStream_t s);
+cute_status mask_bits(const uint8_t* mask, const GridHost& g, uint32_t* bits, hipStream_t s);
+cute_status zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 
 }  // namespace cute
 

@@ -197,7 +197,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
     q.x = a;
     q.y = b;
     q.z = c;
-    q.w = 0.0;
+    q.idx = (uint32_t)i;
+    q.pad = 0u;
     p64[pos] = q;
 }
 

@@ -1,0 +1,435 @@
+// Launch planning shared by the single and the batched counts: decision
+// thresholds of a binning, per-pair geometry of two grids, the proven FP32
+// rounding bands and the LDS layout of a count kernel. Host code only.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "cute_internal.h"
+#include "runtime.h"
+
+namespace cute {
+
+namespace {
+
+constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+constexpr float kBig = 1e30f;
+constexpr double kPiH = 3.14159265358979323846;
+
+float up32(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+float dn32(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+
+bool edges_ok(const double* e, int n, bool mu) {
+    if (!e || n < 1) return false;
+    for (int k = 0; k <= n; k++) {
+        if (!std::isfinite(e[k]) || e[k] < 0.0) return false;
+        if (mu && e[k] > 1.0) return false;
+        if (k > 0 && !(e[k] > e[k - 1])) return false;
+    }
+    return true;
+}
+
+bool is_linear(const double* e, int n) {
+    const double s = (e[n] - e[0]) / n;
+    for (int k = 0; k <= n; k++)
+        if (std::fabs(e[k] - (e[0] + k * s)) > 1e-6 * s) return false;
+    return true;
+}
+
+bool is_log(const double* e, int n) {
+    if (!(e[0] > 0.0)) return false;
+    const double a = std::log2(e[0]), s = (std::log2(e[n]) - a) / n;
+    for (int k = 0; k <= n; k++)
+        if (std::fabs(std::log2(e[k]) - (a + k * s)) > 1e-6 * s) return false;
+    return true;
+}
+
+// Bound on |FP32 squared separation - exact r^2| plus |canonical FP64 value -
+// exact r^2| for a true separation up to r. FP32 components carry absolute
+// errors <= ec (coordinate rounding, origin shift, subtraction); the three-term
+// sum of squares adds <= 3.01 u of itself. The FP64 canonical value has the
+// same structure with ec64 and u64.
+double d2_bound(double r, double ec, double ec64) {
+    const double s3 = std::sqrt(3.0);
+    const double d32 = 2 * s3 * r * ec + 3 * ec * ec + 3.01 * kU32 * (r + s3 * ec) * (r + s3 * ec);
+    const double d64 =
+        2 * s3 * r * ec64 + 3 * ec64 * ec64 + 3.01 * kU64 * (r + s3 * ec64) * (r + s3 * ec64);
+    return d32 + d64;
+}
+
+}  // namespace
+
+cute_status validate_binning(const cute_binning* b) {
+    if (!b) return fail(CUTE_E_INVALID_ARG, "binning is NULL");
+    if (b->kind < CUTE_BIN_MONO || b->kind > CUTE_BIN_THETA)
+        return fail(CUTE_E_INVALID_ARG, "unknown bin kind");
+    if (b->n1 < 1 || b->n1 > 65536) return fail(CUTE_E_INVALID_ARG, "n1 must be in [1, 65536]");
+    if (!edges_ok(b->edges1, b->n1, false))
+        return fail(CUTE_E_INVALID_ARG, "edges1 must be finite, >= 0 and strictly increasing");
+    if (b->kind == CUTE_BIN_THETA && b->edges1[b->n1] > kPiH)
+        return fail(CUTE_E_INVALID_ARG, "theta edges must be <= pi");
+    if (b->kind == CUTE_BIN_RMU || b->kind == CUTE_BIN_SIGMAPI) {
+        if (b->n2 < 1 || b->n2 > 65536) return fail(CUTE_E_INVALID_ARG, "n2 must be in [1, 65536]");
+        if (!edges_ok(b->edges2, b->n2, b->kind == CUTE_BIN_RMU))
+            return fail(CUTE_E_INVALID_ARG,
+                        "edges2 must be finite, >= 0, strictly increasing (mu within [0, 1])");
+        if (b->los != CUTE_LOS_Z && b->los != CUTE_LOS_MIDPOINT)
+            return fail(CUTE_E_INVALID_ARG, "unknown line of sight");
+        if (b->kind == CUTE_BIN_SIGMAPI && b->los != CUTE_LOS_MIDPOINT)
+            return fail(CUTE_E_UNSUPPORTED, "sigma-pi needs the midpoint line of sight");
+        if ((int64_t)b->n1 * b->n2 > (int64_t)1 << 24)
+            return fail(CUTE_E_INVALID_ARG, "too many bins");
+    } else if (b->n2 != 0) {
+        return fail(CUTE_E_INVALID_ARG, "n2 must be 0 for MONO and THETA");
+    }
+    return CUTE_OK;
+}
+
+bool same_binning(const cute_binning* a, const cute_binning* b) {
+    if (a == b) return true;
+    if (a->kind != b->kind || a->n1 != b->n1 || a->n2 != b->n2) return false;
+    if ((a->kind == CUTE_BIN_RMU || a->kind == CUTE_BIN_SIGMAPI) && a->los != b->los) return false;
+    if (memcmp(a->edges1, b->edges1, sizeof(double) * (size_t)(a->n1 + 1)) != 0) return false;
+    if (a->n2 > 0 && memcmp(a->edges2, b->edges2, sizeof(double) * (size_t)(a->n2 + 1)) != 0)
+        return false;
+    return true;
+}
+
+// Thresholds and the bin-estimate constants of a validated binning.
+void plan_binning(const cute_binning* b, Plan& pl) {
+    const int n1 = b->n1, n2 = b->n2 > 0 ? b->n2 : 0;
+    CountArgs& a = pl.a;
+    memset(&a, 0, sizeof(a));
+    switch (b->kind) {
+        case CUTE_BIN_MONO: pl.mode = M_MONO; break;
+        case CUTE_BIN_THETA: pl.mode = M_THETA; break;
+        case CUTE_BIN_RMU: pl.mode = b->los == CUTE_LOS_Z ? M_RMU_Z : M_RMU_MID; break;
+        default: pl.mode = M_SIGMAPI; break;
+    }
+    // canonical thresholds: squared edges (chords of theta)
+    pl.T1.resize(n1 + 1);
+    for (int k = 0; k <= n1; k++) {
+        if (b->kind == CUTE_BIN_THETA) {
+            const double c = 2.0 * std::sin(0.5 * b->edges1[k]);
+            pl.T1[k] = c * c;
+        } else {
+            pl.T1[k] = b->edges1[k] * b->edges1[k];
+        }
+    }
+    if (n2 > 0) {
+        pl.T2.resize(n2 + 1);
+        for (int k = 0; k <= n2; k++) pl.T2[k] = b->edges2[k] * b->edges2[k];
+    } else {
+        pl.T2.assign(1, 0.0);
+    }
+    if (b->kind == CUTE_BIN_SIGMAPI)
+        pl.rmax = std::sqrt(b->edges1[n1] * b->edges1[n1] + b->edges2[n2] * b->edges2[n2]);
+    else if (b->kind == CUTE_BIN_THETA)
+        pl.rmax = 2.0 * std::sin(0.5 * b->edges1[n1]);
+    else
+        pl.rmax = b->edges1[n1];
+
+    a.n1 = n1;
+    a.n2 = n2;
+    a.nbins = n1 * (n2 > 0 ? n2 : 1);
+    a.n1m1 = (float)(n1 - 1);
+    a.n2m1 = (float)(n2 > 0 ? n2 - 1 : 0);
+    a.mu_top_closed = (b->kind == CUTE_BIN_RMU && b->edges2[n2] >= 1.0) ? 1 : 0;
+
+    // dimension-1 estimate
+    const double* e1 = b->edges1;
+    const bool lin1 = is_linear(e1, n1), log1 = !lin1 && is_log(e1, n1);
+    pl.est = log1 ? E_LOG : E_LIN;
+    if (b->kind == CUTE_BIN_SIGMAPI) pl.est = E_LIN;  // sigma estimated linearly
+    {
+        const double lo = e1[0], hi = e1[n1];
+        if (pl.est == E_LOG) {
+            const double la = std::log2(lo), ls = (std::log2(hi) - la) / n1;
+            if (b->kind == CUTE_BIN_THETA) {
+                a.e1a = (float)(1.0 / ls);          // t = log2(theta)
+                a.e1b = (float)(-la / ls);
+            } else {
+                a.e1a = (float)(0.5 / ls);          // t = log2(r^2)
+                a.e1b = (float)(-la / ls);
+            }
+        } else {
+            const double sp = (hi - lo) / n1;
+            a.e1a = (float)(1.0 / sp);
+            a.e1b = (float)(-lo / sp);
+        }
+    }
+    a.bot32 = (float)pl.T1[0];
+    a.top32 = (float)pl.T1[n1];
+
+    // dimension 2 (mu or pi): estimate and the ratio-predicate tables
+    if (n2 > 0) {
+        const double lo = b->edges2[0], hi = b->edges2[n2];
+        const double sp = (hi - lo) / n2;
+        a.e2a = (float)(1.0 / sp);
+        a.e2b = (float)(-lo / sp);
+        a.d2_generic = is_linear(b->edges2, n2) ? 0 : 1;
+        pl.band2.resize(n2);
+        for (int k = 0; k < n2; k++) {
+            float l = pl.T2[k] == 0.0 ? kBig : -(float)pl.T2[k];
+            float h = (k + 1 == n2 && a.mu_top_closed) ? -kBig : -(float)pl.T2[k + 1];
+            pl.band2[k] = make_float2(l, h);
+        }
+        a.nlo2_first = pl.T2[0] == 0.0 ? kBig : -(float)pl.T2[0];
+        a.nhi2_last = a.mu_top_closed ? -kBig : -(float)pl.T2[n2];
+        a.d2lo32 = (float)pl.T2[0];
+        a.d2hi32 = (float)pl.T2[n2];
+        if (b->kind == CUTE_BIN_RMU) a.d2_partial = (pl.T2[0] > 0.0 || !a.mu_top_closed) ? 1 : 0;
+    } else {
+        pl.band2.assign(1, make_float2(0.f, 0.f));
+    }
+}
+
+// Geometry of one pair of grids under a binning: compatibility checks, the
+// stencil radius, the home-tile width limit, the FP32 frame offsets and the
+// inputs of the rounding-error model.
+cute_status plan_item(const GridHost& A, const GridHost& B, bool is_auto, const cute_binning* b,
+                      const Plan& pl, ItemGeom* g) {
+    if (A.geom != B.geom) return fail(CUTE_E_INVALID_ARG, "grids have different geometries");
+    const bool sphere = A.geom == CUTE_GEOM_SPHERE;
+    const bool periodic = A.geom == CUTE_GEOM_BOX_PERIODIC;
+    if (sphere != (b->kind == CUTE_BIN_THETA))
+        return fail(CUTE_E_INVALID_ARG, "THETA binning needs SPHERE grids and vice versa");
+    if (periodic && A.L != B.L) return fail(CUTE_E_INVALID_ARG, "periodic grids with different L");
+    const bool mid = (b->kind == CUTE_BIN_SIGMAPI) ||
+                     (b->kind == CUTE_BIN_RMU && b->los == CUTE_LOS_MIDPOINT);
+    if (mid && periodic) return fail(CUTE_E_UNSUPPORTED, "midpoint line of sight in a periodic box");
+    const double rmax = pl.rmax;
+    if (periodic && !(rmax * (1.0 + 1e-9) < 0.5 * A.L))
+        return fail(CUTE_E_INVALID_ARG, "periodic r_max must be < L/2");
+
+    *g = ItemGeom();
+    g->A = A.view();
+    g->B = B.view();
+    g->geom = (int)A.geom;
+    g->is_auto = is_auto ? 1 : 0;
+    g->periodic = periodic ? 1 : 0;
+    g->L = periodic ? A.L : 0.0;
+
+    // stencil radius
+    const double scale = std::max({A.ext, B.ext, 1e-300});
+    g->Rs = rmax * (1.0 + 1e-9) + 1e-9 * scale;
+    if (sphere) {
+        const double th = b->edges1[b->n1];
+        g->th_s = th * (1.0 + 1e-9) + 1e-12;
+        g->sin_th_s = std::sin(std::min(g->th_s, 0.5 * kPiH));
+    }
+
+    // home-tile width limit
+    int max_w;
+    if (periodic) {
+        // a tile plus its reach must not wrap onto itself in any axis
+        const double reach_y = (A.ay + 2 * g->Rs) / B.ay + 2.0;
+        const double reach_z = (A.az + 2 * g->Rs) / B.az + 2.0;
+        if (reach_y > B.ny || reach_z > B.nz)
+            return fail(CUTE_E_INVALID_ARG,
+                        "periodic grid too coarse for this r_max (build it with r_max set)");
+        const double w = ((B.nx - 2) * B.ax - 2 * g->Rs) / A.ax;
+        max_w = (int)std::floor(w);
+        if (max_w < 1)
+            return fail(CUTE_E_INVALID_ARG,
+                        "periodic grid too coarse for this r_max (build it with r_max set)");
+        max_w = std::min(max_w, std::max(1, (int)std::floor(0.5 * g->Rs / A.ax)));
+    } else if (sphere) {
+        max_w = std::max(1, (int)std::floor(0.5 * g->th_s / A.ax));
+    } else {
+        max_w = std::max(1, (int)std::floor(0.5 * g->Rs / A.ax));
+    }
+    g->max_w = std::min(max_w, 65535);
+
+    // FP32 error model. ec bounds |FP32 coordinate difference - exact
+    // difference| per component: rounding of both FP32 copies (u X_A + u X_B),
+    // the neighbour moved into the home frame, q - off with off = FP32(cA - cB)
+    // or a periodic image shift (u |off| + u (X_B + |off|)), and the final
+    // subtraction (u R).
+    double offmax = 0.0;
+    if (periodic) {
+        offmax = A.L;
+    } else if (!sphere && !is_auto) {
+        offmax = std::max({std::fabs((double)(float)(A.cx - B.cx)),
+                           std::fabs((double)(float)(A.cy - B.cy)),
+                           std::fabs((double)(float)(A.cz - B.cz))});
+    }
+    const bool no_off = is_auto || periodic || sphere;
+    g->offx = no_off ? 0.f : (float)(A.cx - B.cx);
+    g->offy = no_off ? 0.f : (float)(A.cy - B.cy);
+    g->offz = no_off ? 0.f : (float)(A.cz - B.cz);
+    const double Re = rmax * 1.01 + 1e-30;
+    const double extra = offmax > 0.0 ? kU32 * offmax + kU32 * (B.ext + offmax) : 0.0;
+    g->em.ec = 1.0001 * (kU32 * A.ext + kU32 * B.ext + extra + kU32 * Re);
+    g->em.ec64 = 2.0 * kU64 * (A.rawmax + B.rawmax + (periodic ? A.L : 0.0)) * 1.0001;
+    if (mid) {
+        // l = h + ((q - off) + FP32(2 cA)): the roundings of both copies, of the
+        // frame shift, of 2 cA, of the two additions (|l| <= max|p| + max|q|)
+        const double ca = std::max({std::fabs(A.cx), std::fabs(A.cy), std::fabs(A.cz)});
+        g->em.el = 1.0001 * kU32 *
+                   (A.ext + B.ext + extra + 2 * ca + (B.ext + offmax + 2 * ca) + (A.lmax + B.lmax));
+        g->em.el64 = 2.0 * kU64 * (A.lmax + B.lmax);
+        g->lcx = (float)(2.0 * A.cx);
+        g->lcy = (float)(2.0 * A.cy);
+        g->lcz = (float)(2.0 * A.cz);
+    }
+
+    // estimated candidate pairs: nA nB times the stencil's share of B's domain
+    double vol_b, vol_s;
+    if (sphere) {
+        vol_b = std::max(B.nx * B.ax * B.ny * B.ay, 1e-300);  // phi range x cos(theta) range
+        vol_s = kPiH * g->th_s * g->th_s;
+    } else {
+        vol_b = std::max(B.nx * B.ax * B.ny * B.ay * B.nz * B.az, 1e-300);
+        vol_s = 4.0 / 3.0 * kPiH * g->Rs * g->Rs * g->Rs;
+    }
+    g->cost = (double)A.n * (double)B.n * std::min(1.0, 1.5 * vol_s / vol_b) * (is_auto ? 0.5 : 1.0);
+    return CUTE_OK;
+}
+
+// The error model of several items: every term of the bounds grows with each
+// input, so the component-wise maximum bounds every item.
+ErrModel max_err(const ErrModel& x, const ErrModel& y) {
+    ErrModel m;
+    m.ec = std::max(x.ec, y.ec);
+    m.ec64 = std::max(x.ec64, y.ec64);
+    m.el = std::max(x.el, y.el);
+    m.el64 = std::max(x.el64, y.el64);
+    return m;
+}
+
+// FP32 rounding bands of the decision thresholds under the error model em.
+void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
+    CountArgs& a = pl.a;
+    const int n1 = b->n1;
+    const double ec = em.ec, ec64 = em.ec64;
+    const double s3 = std::sqrt(3.0);
+    const double Re = pl.rmax * 1.01 + 1e-30;
+    if (b->kind == CUTE_BIN_SIGMAPI) {
+        pl.band1.resize(n1);
+        for (int k = 0; k < n1; k++) {
+            float lo = pl.T1[k] == 0.0 ? kBig : -(float)pl.T1[k];
+            float hi = -(float)pl.T1[k + 1];
+            pl.band1[k] = make_float2(lo, hi);
+        }
+        a.out_hi = -(float)pl.T1[n1];
+        a.out_lo = pl.T1[0] == 0.0 ? kBig : -(float)pl.T1[0];
+    } else {
+        std::vector<float> lo_e(n1 + 1), hi_e(n1 + 1);
+        for (int k = 0; k <= n1; k++) {
+            const double rk = std::sqrt(pl.T1[k]);
+            const double m = 1.5 * d2_bound(rk * (1.0 + 1e-6) + 2.0 * ec, ec, ec64);
+            lo_e[k] = pl.T1[k] == 0.0 ? -1.0f : up32(pl.T1[k] + m);
+            const double h = pl.T1[k] - m;
+            hi_e[k] = h > 0.0 ? dn32(h) : -1.0f;
+        }
+        pl.band1.resize(n1);
+        for (int k = 0; k < n1; k++) pl.band1[k] = make_float2(lo_e[k], hi_e[k + 1]);
+        a.out_hi = lo_e[n1];
+        a.out_lo = hi_e[0];
+    }
+    if (pl.mode == M_RMU_Z) {
+        // |F - exact| <= 2 sqrt(2) ec r + 3 ec^2 + 8.1 u S, plus the FP64 terms;
+        // r is bounded by the FP32 estimate r (1 + 5u) + sqrt(3) ec
+        const double k1 = 2 * std::sqrt(2.0) * ec + (2 + 2 * s3) * ec64;
+        // the kernel uses delta = dA0 + dA1 r with the v term folded in:
+        // A2 v <= A2 Re r for every pair whose mu decision counts (r < Re)
+        const double a2 = 1.5 * (8.1 * kU32 + 16 * kU64) * 1.0001;
+        a.dA1 = (float)((1.5 * k1 * (1 + 8 * kU32) + a2 * Re) * 1.0001);
+        a.dA0 = (float)(1.5 * (k1 * s3 * ec + 3 * ec * ec + 4 * ec64 * ec64) * 1.0001);
+        a.dA2 = 0.0f;
+    } else if (pl.mode == M_RMU_MID || pl.mode == M_SIGMAPI) {
+        // midpoint line of sight: perturbations of s = p - q (per component
+        // <= ec) and l = p + q (per component <= el) move the ratio predicates
+        // by first-order terms ~ r |s-error| ll and r^2 |l| |l-error|
+        const double es = s3 * ec, esl = s3 * em.el;
+        const double es64 = s3 * ec64, el64 = s3 * em.el64;
+        auto fill = [&](double c_lin, double c_round, double kmax2, float* A0, float* A1, float* A2,
+                        float* B0, float* B1, float* B2, float* C2, float* C0) {
+            // c_lin: multiplier of the first-order terms (4 for mu and sigma, 2 for pi)
+            double a1 = c_lin * (es + es64);
+            double a2 = c_round * (kU32 + kU64);
+            double a0 = 5 * (kU32 + kU64) * kmax2 + 6 * es * es + a1 * s3 * ec + a2 * 3 * ec * ec;
+            double b2 = c_lin * (esl + el64) + 2 * esl * a2;
+            double b1 = 2 * esl * a1 + c_lin * esl * 3.47 * ec + 4 * es * esl;
+            double b0 = 2 * (esl + el64) * kmax2 + 2 * esl * a0 + c_lin * esl * 3 * ec * ec;
+            double c2 = 12 * esl * esl + esl * esl * a2;
+            double c0 = 2 * kmax2 * esl * esl + esl * esl * a0;
+            const double f = 2.0;
+            *A0 = (float)(f * a0);
+            *A1 = (float)(f * a1);
+            *A2 = (float)(f * a2);
+            *B0 = (float)(f * b0);
+            *B1 = (float)(f * b1);
+            *B2 = (float)(f * b2);
+            *C2 = (float)(f * c2);
+            *C0 = (float)(f * c0);
+        };
+        if (b->kind == CUTE_BIN_SIGMAPI) {
+            const double smax2 = pl.T1[n1], pmax2 = pl.T2[b->n2];
+            fill(4.0, 15.5, smax2, &a.sA0, &a.sA1, &a.sA2, &a.sB0, &a.sB1, &a.sB2, &a.sC2, &a.sC0);
+            fill(2.0, 8.2, pmax2, &a.dA0, &a.dA1, &a.dA2, &a.dB0, &a.dB1, &a.dB2, &a.dC2, &a.dC0);
+        } else {
+            fill(4.0, 17.5, 1.0, &a.dA0, &a.dA1, &a.dA2, &a.dB0, &a.dB1, &a.dB2, &a.dC2, &a.dC0);
+        }
+    }
+}
+
+// LDS of a count workgroup of kWgWaves waves: tables, the shared 64-bit
+// histogram, per-wave queues and span buffers (plus extra bytes). About 40 KB
+// per workgroup keeps four workgroups (16 waves) on a CU; the copies of the
+// histogram are cut to fit, then the budget is relaxed for very large
+// histograms (fewer workgroups per CU).
+cute_status plan_lds(Plan& pl, size_t extra) {
+    CountArgs& a = pl.a;
+    const int n1 = a.n1, n2 = a.n2, nbins = a.nbins;
+    const size_t tables = 8 * (size_t)(n1 + 1) + 8 * (size_t)(n2 + 1) + 8 * (size_t)n1 +
+                          8 * (size_t)std::max(n2, 1);
+    const size_t per_wave = 12 * (size_t)kQCap + 16 + 12 * (size_t)kSpanCap;
+    const size_t fixed = tables + (size_t)kWgWaves * per_wave + extra;
+    int C = 0;
+    for (size_t budget : {(size_t)40 * 1024, (size_t)80 * 1024, (size_t)160 * 1024}) {
+        if (fixed + 8 * (size_t)nbins > budget) continue;
+        size_t cmax = (budget - fixed) / (8 * (size_t)nbins);
+        C = 1;
+        while (C * 2 <= (int)std::min<size_t>(cmax, 32)) C *= 2;
+        break;
+    }
+    if (C == 0) return fail(CUTE_E_UNSUPPORTED, "histogram does not fit in LDS");
+    a.copies = C;
+    a.hist_words = nbins * C;
+    pl.lds = fixed + 8 * (size_t)a.hist_words;
+    return CUTE_OK;
+}
+
+void apply_item(const ItemGeom& g, CountArgs* a) {
+    a->A = g.A;
+    a->B = g.B;
+    a->geom = g.geom;
+    a->is_auto = g.is_auto;
+    a->periodic = g.periodic;
+    a->L = g.L;
+    a->Rs = g.Rs;
+    a->th_s = g.th_s;
+    a->sin_th_s = g.sin_th_s;
+    a->offx = g.offx;
+    a->offy = g.offy;
+    a->offz = g.offz;
+    a->lcx = g.lcx;
+    a->lcy = g.lcy;
+    a->lcz = g.lcz;
+}
+
+}  // namespace cute

@@ -113,3 +113,16 @@ def test_count_and_estimators_reject_bad_binnings(lib):
                                   ctypes.byref(rmu.c()), 1,
                                   ells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == cute.E_INVALID_ARG
+
+
+def test_batch_rejects_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    items = (cute.CBatchItem * 1)()
+    # no items, NULL output, NULL grid in an item: all rejected on the host
+    assert lib.cute_batch_create(items, 0, cute.PREC_FP32_EDGE, None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    assert lib.cute_batch_create(items, 1, cute.PREC_FP32_EDGE, None, None) == cute.E_INVALID_ARG
+    assert lib.cute_batch_create(items, 1, cute.PREC_FP32_EDGE, None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    assert b"grid a is NULL" in lib.cute_last_error()
+    assert lib.cute_batch_run(None, 0, None) == cute.E_INVALID_ARG
+    assert lib.cute_batch_layout(None, 0, None, None) == cute.E_INVALID_ARG
+    lib.cute_batch_free(None)

@@ -59,6 +59,75 @@ def cpu_baseline(d, target_s=15.0):
                       "catalog, same r-mu binning, %.1f s" % (pairs, n2, dt)}
 
 
+def batched_leg(cute, torch, dev, runs=1):
+    """The batched mock workload: 256 periodic mocks (2e4 .. 5e5 points, log-
+    uniform, half clustered) and the 100 jackknife catalogs of a 1e6-point base
+    (one 100 x 100 Mpc/h column left out each), every catalog counted with the
+    monopole (30 bins to 150) and the r-mu (40 x 50 bins to 200) binnings:
+    712 autocorrelations, one batch (two persistent launches in one graph)."""
+    import catalogs
+    t0 = time.perf_counter()
+    mocks, base, region = catalogs.config5()
+    L = 1000.0
+    t_gen = time.perf_counter() - t0
+    mono = cute.Binning(cute.BIN_MONO, np.arange(31) * 5.0)
+    rmu = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(51) / 50.0, los=cute.LOS_Z)
+
+    def dgrid(cat):
+        xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (cat.x, cat.y, cat.z)]
+        return cute.build_grid(xyz, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0)
+
+    t0 = time.perf_counter()
+    gm = [dgrid(m) for m in mocks]
+    gb = dgrid(base)
+    torch.cuda.synchronize()
+    t_grid = time.perf_counter() - t0
+    reg = torch.from_numpy(region).to(dev)
+    items = []
+    for g in gm:
+        items += [cute.BatchItem(g, None, mono), cute.BatchItem(g, None, rmu)]
+    for k in range(100):
+        m = (reg == k).to(torch.uint8)
+        items += [cute.BatchItem(gb, None, mono, mask_a=m), cute.BatchItem(gb, None, rmu, mask_a=m)]
+    t0 = time.perf_counter()
+    b = cute.Batch(items, cute.PREC_FP32_EDGE)
+    t_plan = time.perf_counter() - t0
+    log("bench: batched workload, %d items, planned in %.2f s" % (len(items), t_plan))
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(runs):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / runs
+    st = b.stats()
+    # spot checks: two mocks and one jackknife catalog against the single-count path
+    allc = b.counts()
+    ok = True
+    for k in (0, len(items) // 2 - 1, len(items) - 1):
+        it = items[k]
+        w, o = b.layout(k)
+        if it.mask_a is None:
+            ref = cute.count_pairs(it.a, None, it.binning, cute.PREC_FP64).reshape(-1)
+        else:
+            keep = torch.nonzero(it.mask_a == 0).flatten()
+            sub = [torch.from_numpy(np.ascontiguousarray(v)).to(dev)[keep] for v in (base.x, base.y, base.z)]
+            gs = cute.build_grid(sub, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0)
+            ref = cute.count_pairs(gs, None, it.binning, cute.PREC_FP64).reshape(-1)
+            gs.close()
+        ok = ok and bool(np.array_equal(allc[o:o + w], ref))
+    b.close()
+    return {"workload": "256 periodic mocks (2e4..5e5 points) + 100 jackknife catalogs of a 1e6 base, "
+                        "each with monopole (30 bins, r<150) and r-mu (40x50, r<200) DD; 712 items",
+            "items": len(items), "ms_per_run": round(ms, 3), "runs": runs,
+            "pair_evals": int(st["pair_evals"]), "pairs_in_range": int(st["pairs_in_range"]),
+            "gpair_evals_per_s": round(st["pair_evals"] / (ms * 1e-3) / 1e9, 3),
+            "retests": int(st["retests"]), "spot_checks_bit_exact_vs_fp64_single": ok,
+            "host_s": {"generate": round(t_gen, 2), "grids": round(t_grid, 2), "plan": round(t_plan, 2)}}
+
+
 def committed_traffic():
     """HBM bytes per count launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; None otherwise."""
@@ -68,9 +137,12 @@ def committed_traffic():
         return None
     with open(path) as f:
         prof = json.load(f)
-    with open(os.path.join(ROOT, prof["kernel_source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != prof["kernel_source_sha256"]:
-            return None
+    if "kernel_sources_sha256" not in prof:
+        return None
+    for src, sha in prof["kernel_sources_sha256"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None
     return prof["fp32_edge"]["hbm_bytes_per_launch"]
 
 
@@ -81,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched mock/jackknife workload")
     ap.add_argument("--cell-size", type=float, default=0.0,
                     help="cell side of the grid (0 = the library's choice)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -200,6 +274,8 @@ def main():
                      "traffic": committed_traffic(),
                      "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(cute, torch, dev)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(d)

@@ -189,50 +189,109 @@ __device__ uint32_t classify_pair64(const CountArgs& P, const double* T1, const 
 
 // ---------------------------------------------------------------------------
 // FP32 classification with rounding bands.
-// Output: in   -> certainly in bin *bin (same as the canonical decision)
+//
+// Bin estimates are kept as biased integers: the bits of the float 2^23 + k.
+// The host shifts the estimated variable t by s = (b - 1/2) / a, so that
+// fma(t + s, a, 2^23) rounds to 2^23 + floor(t a + b) (for |t a + b| < 2^22);
+// the bits are then clamped as unsigned integers to [2^23, 2^23 + n - 1]
+// (below 2^23 the float bits are smaller, a NaN or a negative float larger,
+// so every estimate lands on a valid index). The low 24 bits are k itself,
+// which v_mad_u32_u24 reads directly, and (bits << 3) plus a pre-biased table
+// address is the table entry: no float-to-int conversion anywhere.
+// Output: in   -> certainly in the estimated bin (same as the canonical decision)
 //         out  -> certainly not counted
-//         else -> ambiguous (to be re-tested); *bin holds the FP32 guess
+//         else -> ambiguous (to be re-tested)
 // tent: the FP32-only decision (bin or kNoBin), used by FP32_ONLY and for
 //       counting flips.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kBias = 0x4B000000u;   // bits of 2^23
+
 struct C32 {
     bool in, out;
-    uint32_t bin;
+    uint32_t kb, kmb;   // biased estimates of dimension 1 and 2 (kmb = kBias for 1-D kinds)
 };
 
+// wave-uniform constants the VALU needs in VGPRs (an fma or med3 can read
+// only one SGPR): the bias (which is also the float 2^23) and the LDS
+// addresses of the band tables minus the bias times 8
+struct Tab32 {
+    uint32_t vbias;      // VGPR copy of kBias
+    uint32_t tb1, tb2;   // LDS byte address of B1 (B2) - (kBias << 3), modulo 2^32
+    float d0;            // VGPR copy of the constant term of the mu band (z line of sight)
+};
+
+typedef float __attribute__((ext_vector_type(2))) f2v;
+typedef const __attribute__((address_space(3))) f2v* lds_f2p;
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p;
+}
+
+__device__ __forceinline__ Tab32 make_tab32(const CountArgs& P, const float2* B1, const float2* B2) {
+    Tab32 t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t.vbias) : "s"(kBias));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t.d0) : "s"(P.dA0p));
+    t.tb1 = lds_addr(B1) - (kBias << 3);
+    t.tb2 = lds_addr(B2) - (kBias << 3);
+    return t;
+}
+
+__device__ __forceinline__ uint32_t med3u(uint32_t x, uint32_t lo_v, uint32_t hi_s) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo_v), "s"(hi_s));
+    return r;
+}
+
+// biased estimate from a shifted variable ts (see above)
+__device__ __forceinline__ uint32_t est_bits(float ts, float a, const Tab32& T, uint32_t top) {
+    return med3u(__float_as_uint(fmaf(ts, a, __uint_as_float(T.vbias))), T.vbias, top);
+}
+
+__device__ __forceinline__ float2 band_at(uint32_t tb, uint32_t kb) {
+    const f2v b = *(lds_f2p)(uintptr_t)((kb << 3) + tb);
+    return make_float2(b.x, b.y);
+}
+
+// flattened bin of an estimate
+__device__ __forceinline__ uint32_t c32_bin(const CountArgs& P, const C32& c) {
+    return __umul24(c.kb, (uint32_t)P.n2p1) + (c.kmb - kBias);
+}
+
 template <int MODE, int EST, bool WANT_TENT>
-__device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
-                                          const float2* B2, float dx, float dy, float dz,
-                                          float lx, float ly, float lz, uint32_t* tent,
-                                          float dA0v) {
+__device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, float dx, float dy,
+                                          float dz, float lx, float ly, float lz, uint32_t* tent) {
     C32 c;
+    c.kmb = kBias;
     float v = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     if (MODE == M_MONO | MODE == M_THETA) {
-        int k = guess1<MODE, EST>(P, v);
-        float2 b = B1[k];
+        float ts;
+        if (MODE == M_THETA) {
+            float ch = __builtin_amdgcn_sqrtf(v);
+            float th = fmaf(ch * v, 1.0f / 24.0f, ch);  // 2 asin(c/2) to third order
+            ts = ((EST == E_LOG) ? __builtin_amdgcn_logf(th) : th) + P.s1;
+        } else if (EST == E_LOG) {
+            ts = __builtin_amdgcn_logf(v) + P.s1;
+        } else {
+            ts = fmaf(v, __builtin_amdgcn_rsqf(v), P.s1);
+        }
+        c.kb = est_bits(ts, P.e1a, T, P.top1);
+        float2 b = band_at(T.tb1, c.kb);
         c.in = (v >= b.x) & (v < b.y);
         c.out = (v >= P.out_hi) | (v < P.out_lo);
-        c.bin = (uint32_t)k;
-        if (WANT_TENT) *tent = (v >= P.bot32 & v < P.top32) ? (uint32_t)k : kNoBin;
+        if (WANT_TENT) *tent = (v >= P.bot32 & v < P.top32) ? c.kb - kBias : kNoBin;
         return c;
     }
     if (MODE == M_RMU_Z) {
         float rinv = __builtin_amdgcn_rsqf(v);
-        float r = v * rinv;
-        int k;
-        if (EST == E_LOG) {
-            k = guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1m1);
-        } else {
-            k = guess_lin(r, P.e1a, P.e1b, P.n1m1);
-        }
-        float mu = fabsf(dz) * rinv;
-        int km = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
+        float ts = (EST == E_LOG) ? __builtin_amdgcn_logf(v) + P.s1 : fmaf(v, rinv, P.s1);
+        c.kb = est_bits(ts, P.e1a, T, P.top1);
+        c.kmb = est_bits(fmaf(fabsf(dz), rinv, P.s2), P.e2a, T, P.top2);
         float dz2 = dz * dz;
-        float2 b = B1[k];
-        float2 m = B2[km];
-        // the v term of the band is folded into the r term on the host
-        // (v <= r_max r wherever the mu decision matters)
-        float delta = fmaf(P.dA1, r, dA0v);
+        float2 b = band_at(T.tb1, c.kb);
+        float2 m = band_at(T.tb2, c.kmb);
+        // band of the mu predicates, linear in r: dA1 r + dA0. With linear r
+        // bins ts = r + s1 and the host folds -dA1 s1 into the constant.
+        float delta = (EST == E_LOG) ? fmaf(P.dA1, v * rinv, T.d0) : fmaf(P.dA1, ts, T.d0);
         float flo = fmaf(m.x, v, dz2);
         float fhi = fmaf(m.y, v, dz2);
         bool rin = (v >= b.x) & (v < b.y);
@@ -241,12 +300,11 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
         // only r decides a clean "out"; a pair outside a partial mu range is
         // re-tested instead (never the case for mu in [0, 1])
         c.out = (v >= P.out_hi) | (v < P.out_lo);
-        c.bin = __umul24((uint32_t)k, (uint32_t)P.n2) + (uint32_t)km;
         if (WANT_TENT) {
             bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;
             if (P.d2_partial) mm = (fmaf(P.nlo2_first, v, dz2) >= 0.0f) & (fmaf(P.nhi2_last, v, dz2) < 0.0f);
-            *tent = (rr & mm) ? c.bin : kNoBin;
+            *tent = (rr & mm) ? c32_bin(P, c) : kNoBin;
         }
         return c;
     }
@@ -255,15 +313,14 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
         float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
         float rinv = __builtin_amdgcn_rsqf(v);
         float r = v * rinv;
-        int k = (EST == E_LOG) ? guess_lin(__builtin_amdgcn_logf(v), P.e1a, P.e1b, P.n1m1)
-                               : guess_lin(r, P.e1a, P.e1b, P.n1m1);
+        float ts = (EST == E_LOG) ? __builtin_amdgcn_logf(v) + P.s1 : r + P.s1;
+        c.kb = est_bits(ts, P.e1a, T, P.top1);
         float w = v * ll;
         float sl2 = sl * sl;
         float lnorm = __builtin_amdgcn_sqrtf(ll);
-        float mu = fabsf(sl) * rinv * __builtin_amdgcn_rcpf(lnorm);
-        int km = guess_lin(mu, P.e2a, P.e2b, P.n2m1);
-        float2 b = B1[k];
-        float2 m = B2[km];
+        c.kmb = est_bits(fmaf(fabsf(sl), rinv * __builtin_amdgcn_rcpf(lnorm), P.s2), P.e2a, T, P.top2);
+        float2 b = band_at(T.tb1, c.kb);
+        float2 m = band_at(T.tb2, c.kmb);
         float delta = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, r, P.dA0)),
                            fmaf(lnorm, fmaf(P.dB2, v, fmaf(P.dB1, r, P.dB0)),
                                 fmaf(P.dC2, v, P.dC0)));
@@ -273,12 +330,11 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
         bool min_ = (flo >= delta) & (fhi <= -delta);
         c.in = rin & min_;
         c.out = (v >= P.out_hi) | (v < P.out_lo);
-        c.bin = __umul24((uint32_t)k, (uint32_t)P.n2) + (uint32_t)km;
         if (WANT_TENT) {
             bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;
             if (P.d2_partial) mm = (fmaf(P.nlo2_first, w, sl2) >= 0.0f) & (fmaf(P.nhi2_last, w, sl2) < 0.0f);
-            *tent = (rr & mm) ? c.bin : kNoBin;
+            *tent = (rr & mm) ? c32_bin(P, c) : kNoBin;
         }
         return c;
     }
@@ -290,16 +346,16 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
     float rll = __builtin_amdgcn_rcpf(ll);
     float sg = __builtin_amdgcn_sqrtf(fmaxf(c2 * rll, 0.0f));
     float pp = __builtin_amdgcn_sqrtf(sl2 * rll);
-    int ks = guess_lin(sg, P.e1a, P.e1b, P.n1m1);
-    int kp = guess_lin(pp, P.e2a, P.e2b, P.n2m1);
+    c.kb = est_bits(sg + P.s1, P.e1a, T, P.top1);
+    c.kmb = est_bits(pp + P.s2, P.e2a, T, P.top2);
     float t = __builtin_amdgcn_sqrtf(v);
     float lnorm = __builtin_amdgcn_sqrtf(ll);
     float ds = fmaf(ll, fmaf(P.sA2, v, fmaf(P.sA1, t, P.sA0)),
                     fmaf(lnorm, fmaf(P.sB2, v, fmaf(P.sB1, t, P.sB0)), fmaf(P.sC2, v, P.sC0)));
     float dp = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, t, P.dA0)),
                     fmaf(lnorm, fmaf(P.dB2, v, fmaf(P.dB1, t, P.dB0)), fmaf(P.dC2, v, P.dC0)));
-    float2 bs = B1[ks];
-    float2 bp = B2[kp];
+    float2 bs = band_at(T.tb1, c.kb);
+    float2 bp = band_at(T.tb2, c.kmb);
     float fslo = fmaf(bs.x, ll, c2), fshi = fmaf(bs.y, ll, c2);
     float fplo = fmaf(bp.x, ll, sl2), fphi = fmaf(bp.y, ll, sl2);
     c.in = (fslo >= ds) & (fshi <= -ds) & (fplo >= dp) & (fphi <= -dp);
@@ -309,10 +365,9 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const float2* B1,
     float fsbot = fmaf(P.out_lo, ll, c2);       // out_lo holds -S2f[0] (or +BIG)
     float fpbot = fmaf(P.nlo2_first, ll, sl2);  // -P2f[0] (or +BIG)
     c.out = (fstop >= ds) | (fptop >= dp) | (fsbot <= -ds) | (fpbot <= -dp);
-    c.bin = __umul24((uint32_t)ks, (uint32_t)P.n2) + (uint32_t)kp;
     if (WANT_TENT) {
         bool ok = (fsbot >= 0.0f) & (fstop < 0.0f) & (fpbot >= 0.0f) & (fptop < 0.0f);
-        *tent = ok ? c.bin : kNoBin;
+        *tent = ok ? c32_bin(P, c) : kNoBin;
     }
     return c;
 }
@@ -354,9 +409,10 @@ __device__ __forceinline__ void hist_add(unsigned long long* hist, uint32_t bin,
     atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], 1ull);
 }
 
-// The same increment with the lane's copy folded into its base pointer.
-__device__ __forceinline__ void hist_add_lane(unsigned long long* lhist, uint32_t bin, uint32_t lc) {
-    atomicAdd(&lhist[bin << lc], 1ull);
+// One increment at an LDS byte address (the lane's copy already folded in).
+__device__ __forceinline__ void lds_add(uint32_t byte_addr) {
+    __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned long long*)(uintptr_t)byte_addr,
+                           1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Re-test up to 64 queued pairs per pass, one per lane, through the canonical
@@ -386,9 +442,10 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
             const float qx = b.x - (P.offx - shift32(code, 0, Lf));
             const float qy = b.y - (P.offy - shift32(code, 1, Lf));
             const float qz = b.z - (P.offz - shift32(code, 2, Lf));
-            (void)classify32<MODE, EST, true>(P, B1, B2, a.x - qx, a.y - qy, a.z - qz,
+            const Tab32 tab = make_tab32(P, B1, B2);
+            (void)classify32<MODE, EST, true>(P, tab, a.x - qx, a.y - qy, a.z - qz,
                                               a.x + (qx + P.lcx), a.y + (qy + P.lcy),
-                                              a.z + (qz + P.lcz), &t, P.dA0);
+                                              a.z + (qz + P.lcz), &t);
         }
         const uint64_t fl = __builtin_amdgcn_ballot_w64(act && k != t);
         if (lane == 0) {
@@ -456,11 +513,11 @@ __device__ __forceinline__ void home_valid(const CountArgs& P, uint32_t h, bool*
 }
 
 template <int MODE, int PREC, int EST, bool PM, bool MASKED, uint32_t U>
-__device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const float2* B1,
-                                       const float2* B2, const double* T1, const double* T2,
-                                       int lane, bool lvalid, bool lmask, uint32_t lj,
-                                       uint32_t lcode, float qx, float qy, float qz, float qlx,
-                                       float qly, float qlz, float dA0v, uint32_t h) {
+__device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const Tab32& T,
+                                       const float2* B1, const float2* B2, const double* T1,
+                                       const double* T2, int lane, bool lvalid, bool lmask,
+                                       uint32_t lj, uint32_t lcode, float qx, float qy, float qz,
+                                       float qlx, float qly, float qlz, uint32_t lb, uint32_t h) {
     float hx[U], hy[U], hz[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -471,7 +528,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const f
     }
     bool hv[U];
     home_valid<PM, U>(P, h, hv);
-    uint32_t bin[U];
+    uint32_t off[U];
     bool cnt[U], amb[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -485,16 +542,19 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const f
         }
         if (PREC == P_FP32O) {
             uint32_t tent;
-            (void)classify32<MODE, EST, true>(P, B1, B2, dx, dy, dz, lx, ly, lz, &tent, dA0v);
+            (void)classify32<MODE, EST, true>(P, T, dx, dy, dz, lx, ly, lz, &tent);
             cnt[u] = act & (tent != kNoBin);
-            bin[u] = tent;
+            off[u] = __umul24(tent, (uint32_t)P.hs2) + lb;
             amb[u] = false;
         } else {
-            const C32 c =
-                classify32<MODE, EST, false>(P, B1, B2, dx, dy, dz, lx, ly, lz, nullptr, dA0v);
+            const C32 c = classify32<MODE, EST, false>(P, T, dx, dy, dz, lx, ly, lz, nullptr);
             cnt[u] = act & c.in;
             amb[u] = act & !(c.in | c.out);
-            bin[u] = c.bin;
+            // LDS byte address of the bin in this lane's copy of the histogram
+            if (MODE == M_MONO || MODE == M_THETA)
+                off[u] = __umul24(c.kb, (uint32_t)P.hs1) + lb;
+            else
+                off[u] = __umul24(c.kb, (uint32_t)P.hs1) + (__umul24(c.kmb, (uint32_t)P.hs2) + lb);
         }
     }
     // one vote for the whole step; the per-pair votes only on the rare path
@@ -505,11 +565,9 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const f
         for (uint32_t u = 0; u < U; u++) any = any | amb[u];
         any_amb = __builtin_amdgcn_ballot_w64(any);
     }
-    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)P.copies);
-    unsigned long long* lhist = W.hist + (lane & (P.copies - 1));
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add_lane(lhist, bin[u], lc);
+        if (cnt[u]) lds_add(off[u]);
     if (PREC == P_FP32E && any_amb) {
         uint64_t m[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -628,9 +686,9 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         }
 #undef CUTE_RUN64
     } else {
-        // a band constant kept in a VGPR (an fma can read only one SGPR)
-        float dA0v;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(dA0v) : "s"(P.dA0));
+        // wave-uniform constants in VGPRs, and this lane's histogram copy
+        const Tab32 tab = make_tab32(P, B1, B2);
+        const uint32_t lb = lds_addr(W.hist) + ((uint32_t)lane & (uint32_t)(P.copies - 1)) * 8u;
         // the neighbour in the home grid's FP32 frame: q - (cA - cB) for two
         // open grids, or its periodic image q + k L (only one of the two is
         // ever non-zero), and q + 2 cA for the midpoint line of sight
@@ -649,11 +707,11 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     {                                                                                              \
         uint32_t h = ts;                                                                           \
         for (; h + U <= te; h += U)                                                                \
-            step32<MODE, PREC, EST, PM, MSK, U>(P, W, B1, B2, T1, T2, lane, lvalid, C.lmask, C.lj,     \
-                                            C.lcode, qx, qy, qz, qlx, qly, qlz, dA0v, h);          \
+            step32<MODE, PREC, EST, PM, MSK, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid, C.lmask,  \
+                                                C.lj, C.lcode, qx, qy, qz, qlx, qly, qlz, lb, h);  \
         for (; h < te; h++)                                                                        \
-            step32<MODE, PREC, EST, PM, MSK, 1>(P, W, B1, B2, T1, T2, lane, lvalid, C.lmask, C.lj,     \
-                                            C.lcode, qx, qy, qz, qlx, qly, qlz, dA0v, h);          \
+            step32<MODE, PREC, EST, PM, MSK, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid, C.lmask,  \
+                                                C.lj, C.lcode, qx, qy, qz, qlx, qly, qlz, lb, h);  \
     }
         if (C.masked) CUTE_RUN32(true) else CUTE_RUN32(false)
 #undef CUTE_RUN32

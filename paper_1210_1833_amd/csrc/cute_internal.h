@@ -96,6 +96,17 @@ struct CountArgs {
     const double* T1;               // n1+1 canonical FP64 thresholds of dim 1
     const double* T2;               // n2+1 canonical FP64 thresholds of dim 2
     int mu_top_closed;              // last mu edge == 1
+    // FP32 bin estimates (biased integers, see the kernels): shifts of the
+    // estimated variables, clamp tops (bits of 2^23 + n - 1), n2 or 1
+    float s1, s2;
+    uint32_t top1, top2;
+    int n2p1;
+    // LDS histogram strides in bytes: dimension 1 (n2p1 << log2 copies << 3)
+    // and dimension 2 (8 << log2 copies)
+    int hs1, hs2;
+    // constant term of the mu band of the z line of sight as the kernel uses
+    // it (dA0 for log r bins, dA0 - dA1 s1 plus its rounding for linear ones)
+    float dA0p;
     // point masks (batched counts): bit i of word i / 32 set = sorted point i
     // excluded; nullptr = no mask
     const uint32_t* mbA;

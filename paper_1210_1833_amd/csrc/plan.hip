@@ -19,6 +19,7 @@ constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 constexpr float kBig = 1e30f;
 constexpr double kPiH = 3.14159265358979323846;
+constexpr uint32_t kBiasBits = 0x4B000000u;       // bits of the float 2^23
 
 float up32(double x) {
     float f = (float)x;
@@ -172,6 +173,12 @@ void plan_binning(const cute_binning* b, Plan& pl) {
     }
     a.bot32 = (float)pl.T1[0];
     a.top32 = (float)pl.T1[n1];
+    // biased FP32 estimates: fma(t + s, a, 2^23) rounds to 2^23 + floor(t a + b)
+    // when s = (b - 1/2) / a; the clamps are the bits of 2^23 + n - 1
+    a.n2p1 = n2 > 0 ? n2 : 1;
+    a.s1 = (float)(((double)a.e1b - 0.5) / (double)a.e1a);
+    a.top1 = kBiasBits + (uint32_t)(n1 - 1);
+    a.top2 = kBiasBits + (uint32_t)(a.n2p1 - 1);
 
     // dimension 2 (mu or pi): estimate and the ratio-predicate tables
     if (n2 > 0) {
@@ -180,6 +187,7 @@ void plan_binning(const cute_binning* b, Plan& pl) {
         a.e2a = (float)(1.0 / sp);
         a.e2b = (float)(-lo / sp);
         a.d2_generic = is_linear(b->edges2, n2) ? 0 : 1;
+        a.s2 = (float)(((double)a.e2b - 0.5) / (double)a.e2a);
         pl.band2.resize(n2);
         for (int k = 0; k < n2; k++) {
             float l = pl.T2[k] == 0.0 ? kBig : -(float)pl.T2[k];
@@ -347,9 +355,18 @@ void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
         // the kernel uses delta = dA0 + dA1 r with the v term folded in:
         // A2 v <= A2 Re r for every pair whose mu decision counts (r < Re)
         const double a2 = 1.5 * (8.1 * kU32 + 16 * kU64) * 1.0001;
-        a.dA1 = (float)((1.5 * k1 * (1 + 8 * kU32) + a2 * Re) * 1.0001);
-        a.dA0 = (float)(1.5 * (k1 * s3 * ec + 3 * ec * ec + 4 * ec64 * ec64) * 1.0001);
+        const double A1 = (1.5 * k1 * (1 + 8 * kU32) + a2 * Re) * 1.0001;
+        const double A0 = 1.5 * (k1 * s3 * ec + 3 * ec * ec + 4 * ec64 * ec64) * 1.0001;
+        a.dA1 = (float)A1;
+        a.dA0 = (float)A0;
         a.dA2 = 0.0f;
+        // with linear r bins the kernel evaluates dA1 ts + dA0p, ts = fl(r + s1):
+        // dA0p = dA0 - dA1 s1, plus dA1 times the rounding of ts (<= u (r + |s1|),
+        // of which u r is inside dA1's margin)
+        if (pl.est == E_LIN)
+            a.dA0p = up32(A0 - A1 * (double)a.s1 + 2.0 * kU32 * A1 * std::fabs((double)a.s1));
+        else
+            a.dA0p = up32(A0);
     } else if (pl.mode == M_RMU_MID || pl.mode == M_SIGMAPI) {
         // midpoint line of sight: perturbations of s = p - q (per component
         // <= ec) and l = p + q (per component <= el) move the ratio predicates
@@ -410,6 +427,8 @@ cute_status plan_lds(Plan& pl, size_t extra) {
     if (C == 0) return fail(CUTE_E_UNSUPPORTED, "histogram does not fit in LDS");
     a.copies = C;
     a.hist_words = nbins * C;
+    a.hs2 = 8 * C;
+    a.hs1 = a.n2p1 * 8 * C;
     pl.lds = fixed + 8 * (size_t)a.hist_words;
     return CUTE_OK;
 }

@@ -274,6 +274,19 @@ def main():
                      "traffic": committed_traffic(),
                      "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
     }
+    # the cell-size tuner on the same data: its choice and the count time with it
+    best, cand = cute.tune_cell_size(xyz, cute.GEOM_BOX_OPEN, bn, r_max=200.0)
+    gt = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0, cell_size=best)
+    tt = []
+    for _ in range(5):
+        _, stt = cute.count_pairs(gt, None, bn, cute.PREC_FP32_EDGE, out=counts, with_stats=True)
+        tt.append(stt["ms_count"])
+    gt.close()
+    tuned_ok = bool(np.array_equal(counts.cpu().numpy().astype(np.uint64), c32))
+    out["tuned_cell"] = {"cell_size": best if best > 0 else "auto", "kernel_ms": round(min(tt), 4),
+                         "pair_evals": int(stt["pair_evals"]), "bit_exact": tuned_ok,
+                         "candidates_ms": {("auto" if k == 0 else round(k, 3)): round(v, 4)
+                                           for k, v in cand.items()}}
     if not args.no_batched:
         out["batched"] = batched_leg(cute, torch, dev)
     if not args.no_cpu_baseline:

@@ -35,7 +35,9 @@
  *  - Pointers are host pointers unless a flag below says otherwise. The
  *    caller owns every array it passes; the library owns grids.
  *  - All device work of a call is issued on the given stream (NULL = the
- *    null stream) and the call returns after that work has finished.
+ *    null stream) and the call returns after that work has finished, except
+ *    cute_batch_run, which only enqueues (and copies to device memory, which
+ *    stay ordered on the stream).
  */
 #ifndef CUTE_H
 #define CUTE_H
@@ -161,6 +163,26 @@ cute_status cute_get_grid_info(const cute_grid* g, cute_grid_info* info);
 cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_binning* bins,
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);
+
+/* Choose the cell side of the cell list of Sec. 3.3 by measurement. The best
+ * side is data dependent (Sec. 3.3), so each candidate side is timed: a grid
+ * of n points (x, y, z, read as for
+ * cute_build_grid with parameters p, cell_size ignored) is built with it and
+ * the autocorrelation under bins is counted (every 8th home tile for
+ * catalogs above 4e5 points), twice, keeping the faster run.
+ * candidates: n_cand sides (0 = the library's density rule); n_cand == 0
+ *   uses {0, r/2, r/3, r/4, r/5, r/6} with r the binning's reach (theta in
+ *   radians for SPHERE).
+ * best: the fastest candidate. ms (nullable): the time of each candidate
+ *   (n_cand entries, 6 for the default set; NaN for a side the geometry
+ *   rejects, e.g. too coarse for a periodic box).
+ * Errors: those of cute_build_grid and cute_count_pairs; CUTE_E_INVALID_ARG
+ * for n_cand outside [0, 64], negative candidates or when no candidate is
+ * usable. */
+cute_status cute_tune_cell_size(const double* x, const double* y, const double* z, int64_t n,
+                                const cute_grid_params* p, const cute_binning* bins,
+                                cute_precision prec, int32_t n_cand, const double* candidates,
+                                void* stream, double* best, double* ms);
 
 /* ---- Batched counts ---------------------------------------------------------
  * The error analyses of Sec. 4 (Fig. 5) need the same pair counts over many

@@ -27,7 +27,7 @@ EST_NATURAL, EST_LS, EST_BOX = range(3)
 BATCH_GRAPH, BATCH_EAGER = range(2)
 
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
-            "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
+            "cute_tune_cell_size", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
@@ -98,6 +98,10 @@ def load():
     lib.cute_count_pairs.restype = ctypes.c_int
     lib.cute_count_pairs.argtypes = [vp, vp, ctypes.POINTER(CBinning), ctypes.c_int, vp,
                                      ctypes.c_int32, ctypes.POINTER(CountStats), vp]
+    lib.cute_tune_cell_size.restype = ctypes.c_int
+    lib.cute_tune_cell_size.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(GridParams),
+                                        ctypes.POINTER(CBinning), ctypes.c_int, ctypes.c_int32, dp,
+                                        vp, dp, dp]
     ip = ctypes.POINTER(ctypes.c_int64)
     lib.cute_batch_create.restype = ctypes.c_int
     lib.cute_batch_create.argtypes = [ctypes.POINTER(CBatchItem), ctypes.c_int32, ctypes.c_int, vp,
@@ -255,6 +259,30 @@ def build_grid(pos, geom: int, box_size: float = 0.0, r_max: float = 0.0,
     _check(lib.cute_build_grid(x, y, z, int(n), ctypes.byref(p), _stream_handle(stream),
                                ctypes.byref(h)))
     return Grid(h, int(n), keep if dev else None)
+
+
+def tune_cell_size(pos, geom: int, binning: Binning, box_size: float = 0.0, r_max: float = 0.0,
+                   prec: int = PREC_FP32_EDGE, candidates=None, stream=None):
+    """cute_tune_cell_size: (best cell side, {candidate: ms}) for the
+    autocorrelation of ``pos`` under ``binning`` (0 = the library's rule)."""
+    lib = load()
+    x, y, z, n, dev, keep = _coords(pos)
+    p = GridParams(int(geom), float(box_size), float(r_max), 0.0, int(dev))
+    cb = binning.c()
+    cand = None if candidates is None else np.ascontiguousarray(candidates, dtype=np.float64)
+    nc = 0 if cand is None else len(cand)
+    ms = np.full(6 if nc == 0 else nc, np.nan)
+    best = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.cute_tune_cell_size(x, y, z, int(n), ctypes.byref(p), ctypes.byref(cb), int(prec), nc,
+                                   None if cand is None else cand.ctypes.data_as(dp),
+                                   _stream_handle(stream), ctypes.byref(best), ms.ctypes.data_as(dp)))
+    if cand is None:
+        r = binning.edges1[-1] if binning.kind == BIN_THETA else (
+            float(np.hypot(binning.edges1[-1], binning.edges2[-1])) if binning.kind == BIN_SIGMAPI
+            else binning.edges1[-1])
+        cand = np.array([0.0] + [r / k for k in (2, 3, 4, 5, 6)])
+    return best.value, dict(zip([float(c) for c in cand], [float(m) for m in ms]))
 
 
 def count_pairs(a: Grid, b: Grid | None, binning: Binning, prec: int = PREC_FP32_EDGE,

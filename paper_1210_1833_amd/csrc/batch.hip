@@ -185,6 +185,19 @@ cute_status create(const cute_batch_item* items, int32_t n_items, cute_precision
             b->tiles[i] = t;
             b->ntiles[i] = nt;
         }
+        a.stencil = nullptr;
+        a.nst = (int)geo[i].stencil.size();
+        if (a.nst > 0) {
+            int4* dst = nullptr;
+            if ((s = owned_alloc(b, &dst, geo[i].stencil.size())) != CUTE_OK) return s;
+            CUTE_HIP(hipMemcpyAsync(dst, geo[i].stencil.data(), geo[i].stencil.size() * sizeof(int4),
+                                    hipMemcpyHostToDevice, hs));
+            a.stencil = dst;
+            // heavy tiles first within the item
+            if ((s = order_tiles(A, B, dst, a.nst, is_auto, geo[i].periodic != 0, &b->tiles[i],
+                                 b->ntiles[i], hs)) != CUTE_OK)
+                return s;
+        }
         a.tiles = b->tiles[i];
         a.ntiles = b->ntiles[i];
         // masks -> sorted-order bits

@@ -67,10 +67,13 @@ extern "C" const char* cute_status_string(cute_status s) {
 
 extern "C" const char* cute_last_error(void) { return g_err.c_str(); }
 
-extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb,
-                                        const cute_binning* bins, cute_precision prec,
-                                        uint64_t* counts, int32_t counts_on_device,
-                                        cute_count_stats* st, void* stream) {
+namespace {
+
+// One pair count; with tile_stride > 1 only every tile_stride-th home tile is
+// counted (the cell-size tuner's sample).
+cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binning* bins,
+                       cute_precision prec, uint64_t* counts, int32_t counts_on_device,
+                       cute_count_stats* st, void* stream, int tile_stride) {
     if (!ga) return fail(CUTE_E_INVALID_ARG, "grid a is NULL");
     if (!counts) return fail(CUTE_E_INVALID_ARG, "counts is NULL");
     cute_status s = validate_binning(bins);
@@ -108,6 +111,14 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     if ((s = tmp.alloc(&dB2, pl.band2.size())) != CUTE_OK) return s;
     if ((s = tmp.alloc(&work, (size_t)nbins + 5)) != CUTE_OK) return s;
     if ((s = tmp.alloc(&dargs, 1)) != CUTE_OK) return s;
+    int4* dst = nullptr;
+    if (!geo.stencil.empty()) {
+        if ((s = tmp.alloc(&dst, geo.stencil.size())) != CUTE_OK) return s;
+        CUTE_HIP(hipMemcpyAsync(dst, geo.stencil.data(), geo.stencil.size() * sizeof(int4),
+                                hipMemcpyHostToDevice, hs));
+    }
+    a.stencil = dst;
+    a.nst = (int)geo.stencil.size();
     CUTE_HIP(hipMemcpyAsync(dT1, pl.T1.data(), pl.T1.size() * 8, hipMemcpyHostToDevice, hs));
     CUTE_HIP(hipMemcpyAsync(dT2, pl.T2.data(), pl.T2.size() * 8, hipMemcpyHostToDevice, hs));
     CUTE_HIP(hipMemcpyAsync(dB1, pl.band1.data(), pl.band1.size() * 8, hipMemcpyHostToDevice, hs));
@@ -125,6 +136,30 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
     uint32_t ntiles = 0;
     if (A.n > 0 && B.n > 0) {
         if ((s = build_tiles(A, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
+    }
+    if ((s = order_tiles(A, B, dst, a.nst, is_auto, geo.periodic != 0, &tiles, ntiles, hs)) !=
+        CUTE_OK) {
+        dfree(tiles, hs);
+        return s;
+    }
+    if (tile_stride > 1 && ntiles > 0) {
+        // keep every tile_stride-th tile (in place: a stream-ordered round trip)
+        std::vector<Tile> h(ntiles);
+        hipError_t e = hipMemcpyAsync(h.data(), tiles, ntiles * sizeof(Tile), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+        if (e != hipSuccess) {
+            dfree(tiles, hs);
+            return hip_status(e, "tile sample");
+        }
+        uint32_t k = 0;
+        for (uint32_t t = 0; t < ntiles; t += (uint32_t)tile_stride) h[k++] = h[t];
+        ntiles = k;
+        e = hipMemcpyAsync(tiles, h.data(), ntiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+        if (e != hipSuccess) {
+            dfree(tiles, hs);
+            return hip_status(e, "tile sample");
+        }
     }
     a.tiles = tiles;
     a.ntiles = ntiles;
@@ -164,6 +199,71 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
         st->pairs_in_range = counts_on_device ? 0 : tot;
     }
     if (hst[3] != ntiles) return fail(CUTE_E_INTERNAL, "not every tile was processed");
+    return CUTE_OK;
+}
+
+}  // namespace
+
+extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb,
+                                        const cute_binning* bins, cute_precision prec,
+                                        uint64_t* counts, int32_t counts_on_device,
+                                        cute_count_stats* st, void* stream) {
+    return count_impl(ga, gb, bins, prec, counts, counts_on_device, st, stream, 1);
+}
+
+extern "C" cute_status cute_tune_cell_size(const double* x, const double* y, const double* z,
+                                           int64_t n, const cute_grid_params* p,
+                                           const cute_binning* bins, cute_precision prec,
+                                           int32_t n_cand, const double* candidates,
+                                           void* stream, double* best, double* ms) {
+    if (!best) return fail(CUTE_E_INVALID_ARG, "best is NULL");
+    if (!p) return fail(CUTE_E_INVALID_ARG, "params is NULL");
+    cute_status s = validate_binning(bins);
+    if (s != CUTE_OK) return s;
+    if (n_cand < 0 || n_cand > 64 || (n_cand > 0 && !candidates))
+        return fail(CUTE_E_INVALID_ARG, "n_cand must be in [0, 64] with candidates given");
+    Plan pl;
+    plan_binning(bins, pl);
+    const double rmax = bins->kind == CUTE_BIN_THETA ? bins->edges1[bins->n1] : pl.rmax;
+    std::vector<double> cand;
+    if (n_cand > 0) {
+        for (int i = 0; i < n_cand; i++) {
+            if (!(candidates[i] >= 0.0) || !std::isfinite(candidates[i]))
+                return fail(CUTE_E_INVALID_ARG, "candidates must be finite and >= 0");
+            cand.push_back(candidates[i]);
+        }
+    } else {
+        cand.push_back(0.0);  // the library's density rule
+        for (double f : {1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6}) cand.push_back(rmax * f);
+    }
+    const int stride = n > 400000 ? 8 : 1;  // sample large catalogs
+    std::vector<uint64_t> counts((size_t)pl.a.nbins);
+    double best_ms = INFINITY;
+    int best_i = -1;
+    for (size_t i = 0; i < cand.size(); i++) {
+        cute_grid_params q = *p;
+        q.cell_size = cand[i];
+        if (q.r_max < rmax) q.r_max = rmax;
+        cute_grid* g = nullptr;
+        s = cute_build_grid(x, y, z, n, &q, stream, &g);
+        double t = INFINITY;
+        if (s == CUTE_OK) {
+            for (int rep = 0; rep < 2 && s == CUTE_OK; rep++) {
+                cute_count_stats st;
+                s = count_impl(g, nullptr, bins, prec, counts.data(), 0, &st, stream, stride);
+                if (s == CUTE_OK) t = std::min(t, st.ms_count);
+            }
+            cute_free_grid(g);
+        }
+        if (s == CUTE_E_OUT_OF_MEMORY || s == CUTE_E_DEVICE) return s;
+        if (ms) ms[i] = s == CUTE_OK ? t : NAN;  // a rejected candidate (too coarse) is NaN
+        if (s == CUTE_OK && t < best_ms) {
+            best_ms = t;
+            best_i = (int)i;
+        }
+    }
+    if (best_i < 0) return fail(CUTE_E_INVALID_ARG, "no candidate cell size is usable");
+    *best = cand[best_i];
     return CUTE_OK;
 }
 

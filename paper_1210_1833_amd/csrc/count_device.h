@@ -870,6 +870,49 @@ __device__ bool gen_spans(const CountArgs& P, const Tile& tl, int lane, SpanBuf&
         return true;
     }
 
+    // 3-D boxes of one geometry: the rows are precomputed offsets
+    if (P.stencil != nullptr) {
+        const cu32p st = (cu32p)(const void*)P.stencil;
+        for (int e = *row; e < P.nst; e++) {
+            if (S.n > room) {
+                *row = e;
+                return false;
+            }
+            const int ody = (int)uni(st[4 * e]), odz = (int)uni(st[4 * e + 1]);
+            const int left = (int)uni(st[4 * e + 2]), right = (int)uni(st[4 * e + 3]);
+            const int byu = cy + ody, bzu = cz + odz;
+            const bool same = P.is_auto && ody == 0 && odz == 0;
+            int x0 = same ? c0 : c0 - left, x1 = c1 + right;
+            int ry = byu, rz = bzu, ky = 0, kz = 0;
+            if (P.periodic) {
+                ky = floordiv(byu, B.ny);
+                kz = floordiv(bzu, B.nz);
+                ry = byu - ky * B.ny;
+                rz = bzu - kz * B.nz;
+                // never more than one full turn of the row
+                x1 = x1 < x0 + B.nx - 1 ? x1 : x0 + B.nx - 1;
+            } else {
+                if (byu < 0 || byu >= B.ny || bzu < 0 || bzu >= B.nz) continue;
+                x0 = x0 < 0 ? 0 : x0;
+                x1 = x1 > B.nx - 1 ? B.nx - 1 : x1;
+                if (x0 > x1) continue;
+            }
+            const uint32_t rb = (uint32_t)B.nx * ((uint32_t)ry + (uint32_t)B.ny * (uint32_t)rz);
+            int a0 = x0;
+            while (a0 <= x1) {
+                const int kx = P.periodic ? floordiv(a0, B.nx) : 0;
+                const int lim = P.periodic ? (kx + 1) * B.nx - 1 : x1;
+                const int a1 = x1 < lim ? x1 : lim;
+                const uint32_t code =
+                    (uint32_t)(kx + 1) | ((uint32_t)(ky + 1) << 2) | ((uint32_t)(kz + 1) << 4);
+                push_cells(S, lane, cs, rb, a0 - kx * B.nx, a1 - kx * B.nx, code,
+                           same && kx == 0 && a0 == c0, ts, te);
+                a0 = a1 + 1;
+            }
+        }
+        return true;
+    }
+
     // 3-D boxes: the tile box, grown by R, selects rows of neighbour cells
     const double R = P.Rs;
     const double xlo = A.ox + c0 * A.ax, xhi = A.ox + (c1 + 1) * A.ax;

@@ -17,6 +17,8 @@
 //    queue that is drained 64 pairs at a time through the canonical FP64
 //    predicates, so the counts equal the FP64 ones.
 //  - FP32_ONLY: FP32 decisions only.
+#include <hipcub/hipcub.hpp>
+
 #include "count_device.h"
 
 namespace cute {
@@ -212,6 +214,92 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
         }
     }
     if (open) tiles[o++] = cur;
+}
+
+namespace {
+
+// Estimated cost of each home tile for the longest-first order: candidate
+// pairs (home points times the neighbours its stencil rows hold) plus a
+// per-row and a per-tile overhead, in pair evaluations. Uses the precomputed
+// neighbour rows (grids of one geometry), so it is integer work.
+__global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                   const uint32_t* __restrict__ cs, int any, int nx,
+                                                   int ny, int nz, const int4* __restrict__ st,
+                                                   int nst, int periodic, int is_auto,
+                                                   uint32_t* __restrict__ key) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const int c0 = (int)(tl.c0c1 & 0xffffu), c1 = (int)(tl.c0c1 >> 16);
+    const int cy = (int)(tl.row % (uint32_t)any), cz = (int)(tl.row / (uint32_t)any);
+    uint64_t nb = 0, rows = 0;
+    for (int e = 0; e < nst; e++) {
+        const int4 o = st[e];
+        int by = cy + o.x, bz = cz + o.y;
+        const bool same = is_auto && o.x == 0 && o.y == 0;
+        int x0 = same ? c0 : c0 - o.z, x1 = c1 + o.w;
+        if (periodic) {
+            by -= floordiv(by, ny) * ny;
+            bz -= floordiv(bz, nz) * nz;
+            x1 = x1 < x0 + nx - 1 ? x1 : x0 + nx - 1;
+        } else {
+            if (by < 0 || by >= ny || bz < 0 || bz >= nz) continue;
+            x0 = x0 < 0 ? 0 : x0;
+            x1 = x1 > nx - 1 ? nx - 1 : x1;
+            if (x0 > x1) continue;
+        }
+        const uint32_t rb = (uint32_t)nx * ((uint32_t)by + (uint32_t)ny * (uint32_t)bz);
+        for (int a0 = x0; a0 <= x1;) {
+            const int kx = floordiv(a0, nx);
+            const int lim = (kx + 1) * nx - 1;
+            const int a1 = x1 < lim ? x1 : lim;
+            nb += cs[rb + (uint32_t)(a1 - kx * nx) + 1u] - cs[rb + (uint32_t)(a0 - kx * nx)];
+            a0 = a1 + 1;
+        }
+        rows++;
+    }
+    const uint64_t c = (uint64_t)(tl.end - tl.start) * nb + 128ull * rows + 2048ull;
+    key[t] = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
+}
+
+}  // namespace
+
+// Reorder tiles longest first (estimated cost, descending): the persistent
+// waves take the heavy tiles early and the light ones fill the tail.
+cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stencil, int nst,
+                        bool is_auto, bool periodic, Tile** tiles, uint32_t ntiles,
+                        hipStream_t s) {
+    if (ntiles < 2 || stencil == nullptr || nst <= 0) return CUTE_OK;
+    TempList tmp(s);
+    uint32_t *k0 = nullptr, *k1 = nullptr;
+    Tile* t1 = nullptr;
+    cute_status st;
+    if ((st = tmp.alloc(&k0, ntiles)) != CUTE_OK) return st;
+    if ((st = tmp.alloc(&k1, ntiles)) != CUTE_OK) return st;
+    if ((st = dalloc(&t1, ntiles, s)) != CUTE_OK) return st;
+    const unsigned nb = (ntiles + 255u) / 256u;
+    hipLaunchKernelGGL(k_tile_cost, dim3(nb), dim3(256), 0, s, *tiles, ntiles, B.cstart, A.ny, B.nx,
+                       B.ny, B.nz, stencil, nst, periodic ? 1 : 0, is_auto ? 1 : 0, k0);
+    hipError_t e = hipGetLastError();
+    size_t bytes = 0;
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, k0, k1, *tiles, t1,
+                                                         (int)ntiles, 0, 32, s);
+    void* temp = nullptr;
+    if (e == hipSuccess && (st = tmp.alloc(reinterpret_cast<unsigned char**>(&temp), bytes)) != CUTE_OK) {
+        dfree(t1, s);
+        return st;
+    }
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairsDescending(temp, bytes, k0, k1, *tiles, t1,
+                                                         (int)ntiles, 0, 32, s);
+    if (e != hipSuccess) {
+        dfree(t1, s);
+        return hip_status(e, "tile order");
+    }
+    dfree(*tiles, s);
+    *tiles = t1;
+    return CUTE_OK;
 }
 
 cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,

@@ -107,6 +107,9 @@ struct CountArgs {
     // constant term of the mu band of the z line of sight as the kernel uses
     // it (dA0 for log r bins, dA0 - dA1 s1 plus its rounding for linear ones)
     float dA0p;
+    // precomputed neighbour rows (see ItemGeom::stencil), or nullptr
+    const int4* stencil;
+    int nst;
     // point masks (batched counts): bit i of word i / 32 set = sorted point i
     // excluded; nullptr = no mask
     const uint32_t* mbA;
@@ -163,6 +166,10 @@ struct ItemGeom {
     int max_w = 1;       // home-tile width limit in cells
     ErrModel em;
     double cost = 0.0;   // estimated candidate pairs
+    // rows of neighbour cells as offsets from the home row (3-D grids of one
+    // geometry): (dy, dz, cells left of c0, cells right of c1); empty when
+    // the kernel must derive the rows itself
+    std::vector<int4> stencil;
 };
 
 // A count launch: thresholds, band tables and the binning's kernel constants.
@@ -197,6 +204,12 @@ cute_status exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, hipStrea
 // cells); *tiles is a stream-ordered allocation owned by the caller
 cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
                         uint32_t* ntiles);
+
+// reorder *tiles longest first by estimated cost (needs the precomputed
+// neighbour rows on the device; a no-op without them)
+cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stencil, int nst,
+                        bool is_auto, bool periodic, Tile** tiles, uint32_t ntiles,
+                        hipStream_t s);
 
 // persistent count launch; *grid_used receives the number of workgroups
 cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int wg_waves,

@@ -294,6 +294,32 @@ cute_status plan_item(const GridHost& A, const GridHost& B, bool is_auto, const 
         g->lcz = (float)(2.0 * A.cz);
     }
 
+    // Neighbour rows as offsets, when both grids have one geometry (always
+    // for an autocorrelation): the gap between the home row and the row at
+    // offset (dy, dz) is (|dy| - 1) a_y by (|dz| - 1) a_z, and the cells
+    // within R of the tile's x-range [c0, c1] are c0 - ceil(w / a_x) ..
+    // c1 + 1 + floor(w / a_x) with w^2 = R^2 - gap^2. Rounded outward, so the
+    // rows and cells are a superset of those the exact distances select.
+    const bool same_geom = !sphere && A.nx == B.nx && A.ny == B.ny && A.nz == B.nz &&
+                           A.ox == B.ox && A.oy == B.oy && A.oz == B.oz && A.ax == B.ax &&
+                           A.ay == B.ay && A.az == B.az;
+    if (same_geom) {
+        const double R = g->Rs * (1.0 + 1e-12);
+        const int ry = (int)std::ceil(R / A.ay) + 1, rz = (int)std::ceil(R / A.az) + 1;
+        for (int dz = -rz; dz <= rz; dz++)
+            for (int dy = -ry; dy <= ry; dy++) {
+                if (is_auto && (dz < 0 || (dz == 0 && dy < 0))) continue;
+                const double gy = std::max(0, std::abs(dy) - 1) * A.ay;
+                const double gz = std::max(0, std::abs(dz) - 1) * A.az;
+                const double rem = R * R - gy * gy - gz * gz;
+                if (rem <= 0.0) continue;
+                const double wc = std::sqrt(rem) / A.ax * (1.0 + 1e-12) + 1e-9;
+                const int left = (int)std::ceil(wc), right = (int)std::floor(wc) + 1;
+                g->stencil.push_back(make_int4(dy, dz, left, right));
+            }
+        if (g->stencil.size() > 65536) g->stencil.clear();
+    }
+
     // estimated candidate pairs: nA nB times the stencil's share of B's domain
     double vol_b, vol_s;
     if (sphere) {

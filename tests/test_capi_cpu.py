@@ -126,3 +126,24 @@ def test_batch_rejects_bad_arguments(lib):
     assert lib.cute_batch_run(None, 0, None) == cute.E_INVALID_ARG
     assert lib.cute_batch_layout(None, 0, None, None) == cute.E_INVALID_ARG
     lib.cute_batch_free(None)
+
+
+def test_tune_cell_size_rejects_bad_arguments(lib):
+    x = np.zeros(4)
+    p = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0)
+    b = cute.Binning(cute.BIN_MONO, [0.0, 1.0, 2.0]).c()
+    best = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    bad = np.array([-1.0])
+    # NULL best, NULL params, negative candidate, too many candidates
+    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
+                                   ctypes.byref(b), 1, 0, None, None, None, None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, None,
+                                   ctypes.byref(b), 1, 0, None, None, ctypes.byref(best),
+                                   None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
+                                   ctypes.byref(b), 1, 1, bad.ctypes.data_as(dp), None,
+                                   ctypes.byref(best), None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
+                                   ctypes.byref(b), 1, 65, bad.ctypes.data_as(dp), None,
+                                   ctypes.byref(best), None) == cute.E_INVALID_ARG

@@ -275,3 +275,22 @@ def test_multipoles_match_exact_rationals():
         w = est.multipole_weights_abs(mu, ell)
         scale = np.abs(xi) @ w
         assert np.all(np.abs(got[a] - ref[a]) <= 1e-12 * scale + 1e-300)
+
+
+def test_tuned_cell_size_counts_match_oracle():
+    """The cell-size tuner returns one of its candidates with a time for each;
+    counting with the chosen side gives the oracle's counts."""
+    d, _ = catalogs.config2(n_centres=150, per_blob=40, n_rand=10, box=300.0)
+    re_, me = np.linspace(0, 40, 9), np.linspace(0, 1, 11)
+    bn = cute.Binning(cute.BIN_RMU, re_, me)
+    best, times = cute.tune_cell_size(d, cute.GEOM_BOX_OPEN, bn)
+    say("tuned cell", best, times)
+    assert best in times and all(np.isfinite(v) and v > 0 for v in times.values())
+    got = gpu_counts(d, None, bn, cute.PREC_FP32_EDGE, cute.GEOM_BOX_OPEN, r_max=40.0, cell=best)
+    np.testing.assert_array_equal(got, oracle.count_pairs(d, None, obin(cute.BIN_RMU, re_, me)))
+    # explicit candidates, one of them too coarse for a periodic box of side 100
+    u = catalogs.uniform_box(3000, 100.0, seed=5)
+    mb = cute.Binning(cute.BIN_MONO, np.linspace(0, 20, 11))
+    best, times = cute.tune_cell_size(u, cute.GEOM_BOX_PERIODIC, mb, box_size=100.0,
+                                      candidates=[5.0, 10.0, 60.0])
+    assert best in (5.0, 10.0) and math.isnan(times[60.0])

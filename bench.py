@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched mock/jackknife workload")
+    ap.add_argument("--no-tune", action="store_true", help="skip the cell-size tuner leg")
     ap.add_argument("--cell-size", type=float, default=0.0,
                     help="cell side of the grid (0 = the library's choice)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -275,6 +276,18 @@ def main():
                      "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
     }
     # the cell-size tuner on the same data: its choice and the count time with it
+    if not args.no_tune:
+        out["tuned_cell"] = tuned_leg(cute, xyz, bn, counts, c32)
+    if not args.no_batched:
+        out["batched"] = batched_leg(cute, torch, dev)
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(d)
+    print(json.dumps(out), flush=True)
+
+
+def tuned_leg(cute, xyz, bn, counts, c32):
+    """cute_tune_cell_size on the benchmark data, then the count with its choice."""
     best, cand = cute.tune_cell_size(xyz, cute.GEOM_BOX_OPEN, bn, r_max=200.0)
     gt = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0, cell_size=best)
     tt = []
@@ -283,16 +296,10 @@ def main():
         tt.append(stt["ms_count"])
     gt.close()
     tuned_ok = bool(np.array_equal(counts.cpu().numpy().astype(np.uint64), c32))
-    out["tuned_cell"] = {"cell_size": best if best > 0 else "auto", "kernel_ms": round(min(tt), 4),
-                         "pair_evals": int(stt["pair_evals"]), "bit_exact": tuned_ok,
-                         "candidates_ms": {("auto" if k == 0 else round(k, 3)): round(v, 4)
-                                           for k, v in cand.items()}}
-    if not args.no_batched:
-        out["batched"] = batched_leg(cute, torch, dev)
-    if not args.no_cpu_baseline:
-        log("bench: cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(d)
-    print(json.dumps(out), flush=True)
+    return {"cell_size": best if best > 0 else "auto", "kernel_ms": round(min(tt), 4),
+            "pair_evals": int(stt["pair_evals"]), "bit_exact": tuned_ok,
+            "candidates_ms": {("auto" if k == 0 else round(k, 3)): round(v, 4)
+                              for k, v in cand.items()}}
 
 
 if __name__ == "__main__":

@@ -213,7 +213,11 @@ cute_status create(const cute_batch_item* items, int32_t n_items, cute_precision
             uint8_t* tmp = nullptr;
             if (!it.masks_on_device) {
                 if ((s = dalloc(&tmp, n, hs)) != CUTE_OK) return s;
-                CUTE_HIP(hipMemcpyAsync(tmp, src, n, hipMemcpyHostToDevice, hs));
+                const hipError_t e = hipMemcpyAsync(tmp, src, n, hipMemcpyHostToDevice, hs);
+                if (e != hipSuccess) {
+                    dfree(tmp, hs);
+                    return hip_status(e, "mask copy");
+                }
                 src = tmp;
             }
             s = mask_bits(src, *gh[side], mb, hs);

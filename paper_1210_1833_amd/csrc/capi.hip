@@ -99,35 +99,38 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     if ((s = ensure_device_ready(&dev)) != CUTE_OK) return s;
     hipStream_t hs = (hipStream_t)stream;
 
-    // ---- device buffers ----------------------------------------------------
+    // ---- device buffers: one block, filled by one copy ------------------------
+    // [T1 | T2 | B1 | B2 | stencil | args | counts, stats[4], head]
+    auto up16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+    const size_t oT1 = 0;
+    const size_t oT2 = oT1 + up16(pl.T1.size() * 8);
+    const size_t oB1 = oT2 + up16(pl.T2.size() * 8);
+    const size_t oB2 = oB1 + up16(pl.band1.size() * 8);
+    const size_t oST = oB2 + up16(pl.band2.size() * 8);
+    const size_t oAR = oST + up16(geo.stencil.size() * sizeof(int4));
+    const size_t oWK = oAR + up16(sizeof(CountArgs));
+    const size_t total = oWK + ((size_t)nbins + 5) * 8;
     TempList tmp(hs);
-    double *dT1, *dT2;
-    float2 *dB1, *dB2;
-    unsigned long long* work;  // counts[nbins], stats[4], head
-    CountArgs* dargs;
-    if ((s = tmp.alloc(&dT1, pl.T1.size())) != CUTE_OK) return s;
-    if ((s = tmp.alloc(&dT2, pl.T2.size())) != CUTE_OK) return s;
-    if ((s = tmp.alloc(&dB1, pl.band1.size())) != CUTE_OK) return s;
-    if ((s = tmp.alloc(&dB2, pl.band2.size())) != CUTE_OK) return s;
-    if ((s = tmp.alloc(&work, (size_t)nbins + 5)) != CUTE_OK) return s;
-    if ((s = tmp.alloc(&dargs, 1)) != CUTE_OK) return s;
-    int4* dst = nullptr;
-    if (!geo.stencil.empty()) {
-        if ((s = tmp.alloc(&dst, geo.stencil.size())) != CUTE_OK) return s;
-        CUTE_HIP(hipMemcpyAsync(dst, geo.stencil.data(), geo.stencil.size() * sizeof(int4),
-                                hipMemcpyHostToDevice, hs));
-    }
+    unsigned char* blob = nullptr;
+    if ((s = tmp.alloc(&blob, total)) != CUTE_OK) return s;
+    std::vector<unsigned char> hb(oAR);
+    memcpy(hb.data() + oT1, pl.T1.data(), pl.T1.size() * 8);
+    memcpy(hb.data() + oT2, pl.T2.data(), pl.T2.size() * 8);
+    memcpy(hb.data() + oB1, pl.band1.data(), pl.band1.size() * 8);
+    memcpy(hb.data() + oB2, pl.band2.data(), pl.band2.size() * 8);
+    if (!geo.stencil.empty())
+        memcpy(hb.data() + oST, geo.stencil.data(), geo.stencil.size() * sizeof(int4));
+    CUTE_HIP(hipMemcpyAsync(blob, hb.data(), oAR, hipMemcpyHostToDevice, hs));
+    CUTE_HIP(hipMemsetAsync(blob + oWK, 0, ((size_t)nbins + 5) * 8, hs));
+    unsigned long long* work = reinterpret_cast<unsigned long long*>(blob + oWK);
+    CountArgs* dargs = reinterpret_cast<CountArgs*>(blob + oAR);
+    const int4* dst = geo.stencil.empty() ? nullptr : reinterpret_cast<const int4*>(blob + oST);
     a.stencil = dst;
     a.nst = (int)geo.stencil.size();
-    CUTE_HIP(hipMemcpyAsync(dT1, pl.T1.data(), pl.T1.size() * 8, hipMemcpyHostToDevice, hs));
-    CUTE_HIP(hipMemcpyAsync(dT2, pl.T2.data(), pl.T2.size() * 8, hipMemcpyHostToDevice, hs));
-    CUTE_HIP(hipMemcpyAsync(dB1, pl.band1.data(), pl.band1.size() * 8, hipMemcpyHostToDevice, hs));
-    CUTE_HIP(hipMemcpyAsync(dB2, pl.band2.data(), pl.band2.size() * 8, hipMemcpyHostToDevice, hs));
-    CUTE_HIP(hipMemsetAsync(work, 0, ((size_t)nbins + 5) * 8, hs));
-    a.T1 = dT1;
-    a.T2 = dT2;
-    a.band1 = dB1;
-    a.band2 = dB2;
+    a.T1 = reinterpret_cast<const double*>(blob + oT1);
+    a.T2 = reinterpret_cast<const double*>(blob + oT2);
+    a.band1 = reinterpret_cast<const float2*>(blob + oB1);
+    a.band2 = reinterpret_cast<const float2*>(blob + oB2);
     a.counts = work;
     a.stats = work + nbins;
     a.work_head = reinterpret_cast<uint32_t*>(work + nbins + 4);
@@ -166,19 +169,18 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     a.self = dargs;
     CUTE_HIP(hipMemcpyAsync(dargs, &a, sizeof(a), hipMemcpyHostToDevice, hs));
 
-    double ms = 0.0;
+    // launch, then the copies, then one wait (the end event is read after it)
     int grid = 0;
+    EventTimer timer(hs);
     if (ntiles > 0) {
-        EventTimer timer(hs);
         s = launch_count(a, pl.mode, (int)prec, pl.est, kWgWaves, pl.lds, hs, &grid);
         if (s != CUTE_OK) {
             dfree(tiles, hs);
             return s;
         }
-        ms = timer.stop_ms();
     }
+    timer.stop();
     dfree(tiles, hs);
-
     if (counts_on_device) {
         CUTE_HIP(hipMemcpyAsync(counts, work, (size_t)nbins * 8, hipMemcpyDeviceToDevice, hs));
     } else {
@@ -187,6 +189,7 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     unsigned long long hst[4] = {0, 0, 0, 0};
     CUTE_HIP(hipMemcpyAsync(hst, work + nbins, sizeof(hst), hipMemcpyDeviceToHost, hs));
     CUTE_HIP(hipStreamSynchronize(hs));
+    const double ms = ntiles > 0 ? timer.elapsed_ms() : 0.0;
     if (st) {
         st->pair_evals = hst[0];
         st->retests = hst[1];

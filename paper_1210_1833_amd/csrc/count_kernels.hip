@@ -17,7 +17,9 @@
 //    queue that is drained 64 pairs at a time through the canonical FP64
 //    predicates, so the counts equal the FP64 ones.
 //  - FP32_ONLY: FP32 decisions only.
-#include <hipcub/hipcub.hpp>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "count_device.h"
 
@@ -106,11 +108,26 @@ cute_status launch_one(const CountArgs& a, int wg_waves, size_t lds, hipStream_t
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute");
     }
+    // occupancy of this variant at this LDS size, queried once per device
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, size_t>, std::pair<int, int>> cache;
     int dev = 0, ncu = 0, per_cu = 0;
     CUTE_HIP(hipGetDevice(&dev));
-    CUTE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    CUTE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wg_waves, lds));
-    if (per_cu < 1) per_cu = 1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(std::make_tuple(dev, wg_waves, lds));
+        if (it != cache.end()) {
+            ncu = it->second.first;
+            per_cu = it->second.second;
+        }
+    }
+    if (ncu == 0) {
+        CUTE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        CUTE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wg_waves, lds));
+        if (per_cu < 1) per_cu = 1;
+        std::lock_guard<std::mutex> lk(mu);
+        cache[std::make_tuple(dev, wg_waves, lds)] = std::make_pair(ncu, per_cu);
+    }
     int64_t want = (int64_t)per_cu * ncu;
     int64_t need = ((int64_t)a.ntiles + wg_waves - 1) / wg_waves;
     int grid = (int)(want < need ? want : need);
@@ -222,11 +239,15 @@ namespace {
 // pairs (home points times the neighbours its stencil rows hold) plus a
 // per-row and a per-tile overhead, in pair evaluations. Uses the precomputed
 // neighbour rows (grids of one geometry), so it is integer work.
+constexpr uint32_t kCostBuckets = 256;
+
 __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tiles, uint32_t ntiles,
                                                    const uint32_t* __restrict__ cs, int any, int nx,
                                                    int ny, int nz, const int4* __restrict__ st,
                                                    int nst, int periodic, int is_auto,
-                                                   uint32_t* __restrict__ key) {
+                                                   uint32_t* __restrict__ key,
+                                                   uint32_t* __restrict__ rank,
+                                                   uint32_t* __restrict__ hist) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     const Tile tl = tiles[t];
@@ -258,8 +279,35 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
         }
         rows++;
     }
+    // bucket on a log scale, 8 per octave, largest cost first (bucket 0);
+    // log2(c) is in [11, 64)
     const uint64_t c = (uint64_t)(tl.end - tl.start) * nb + 128ull * rows + 2048ull;
-    key[t] = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
+    const float lc = (__builtin_amdgcn_logf((float)c) - 11.0f) * 8.0f;
+    const uint32_t b = kCostBuckets - 1u - (uint32_t)fminf(fmaxf(lc, 0.0f), (float)(kCostBuckets - 1));
+    key[t] = b;
+    rank[t] = atomicAdd(&hist[b], 1u);
+}
+
+// Scatter the tiles into bucket order: every block scans the bucket counts in
+// LDS (kCostBuckets of them), then each tile goes to its bucket's offset plus
+// its rank within the bucket.
+__global__ __launch_bounds__(256) void k_tile_scatter(const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                      const uint32_t* __restrict__ key,
+                                                      const uint32_t* __restrict__ rank,
+                                                      const uint32_t* __restrict__ hist,
+                                                      Tile* __restrict__ out) {
+    __shared__ uint32_t off[kCostBuckets];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t b = 0; b < kCostBuckets; b++) {
+            off[b] = acc;
+            acc += hist[b];
+        }
+    }
+    __syncthreads();
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    out[off[key[t]] + rank[t]] = tiles[t];
 }
 
 }  // namespace
@@ -271,28 +319,23 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
                         hipStream_t s) {
     if (ntiles < 2 || stencil == nullptr || nst <= 0) return CUTE_OK;
     TempList tmp(s);
-    uint32_t *k0 = nullptr, *k1 = nullptr;
+    uint32_t *key = nullptr, *rank = nullptr, *hist = nullptr;
     Tile* t1 = nullptr;
     cute_status st;
-    if ((st = tmp.alloc(&k0, ntiles)) != CUTE_OK) return st;
-    if ((st = tmp.alloc(&k1, ntiles)) != CUTE_OK) return st;
+    if ((st = tmp.alloc(&key, ntiles)) != CUTE_OK) return st;
+    if ((st = tmp.alloc(&rank, ntiles)) != CUTE_OK) return st;
+    if ((st = tmp.alloc(&hist, kCostBuckets)) != CUTE_OK) return st;
+    CUTE_HIP(hipMemsetAsync(hist, 0, kCostBuckets * sizeof(uint32_t), s));
     if ((st = dalloc(&t1, ntiles, s)) != CUTE_OK) return st;
     const unsigned nb = (ntiles + 255u) / 256u;
     hipLaunchKernelGGL(k_tile_cost, dim3(nb), dim3(256), 0, s, *tiles, ntiles, B.cstart, A.ny, B.nx,
-                       B.ny, B.nz, stencil, nst, periodic ? 1 : 0, is_auto ? 1 : 0, k0);
+                       B.ny, B.nz, stencil, nst, periodic ? 1 : 0, is_auto ? 1 : 0, key, rank, hist);
     hipError_t e = hipGetLastError();
-    size_t bytes = 0;
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, k0, k1, *tiles, t1,
-                                                         (int)ntiles, 0, 32, s);
-    void* temp = nullptr;
-    if (e == hipSuccess && (st = tmp.alloc(reinterpret_cast<unsigned char**>(&temp), bytes)) != CUTE_OK) {
-        dfree(t1, s);
-        return st;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(256), 0, s, *tiles, ntiles, key, rank,
+                           hist, t1);
+        e = hipGetLastError();
     }
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairsDescending(temp, bytes, k0, k1, *tiles, t1,
-                                                         (int)ntiles, 0, 32, s);
     if (e != hipSuccess) {
         dfree(t1, s);
         return hip_status(e, "tile order");

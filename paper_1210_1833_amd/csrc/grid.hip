@@ -450,8 +450,11 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
                            g.cstart, g.cx, g.cy, g.cz, g.p32, g.p64);
         if (hipGetLastError() != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "scatter launch"));
     }
-    g.ms_build = timer.stop_ms();
-    if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "build sync"));
+    // the end event follows the last kernel: waiting for it waits for the build
+    timer.stop();
+    const hipError_t we = timer.b ? hipEventSynchronize(timer.b) : hipStreamSynchronize(s);
+    if (we != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "build sync"));
+    g.ms_build = timer.elapsed_ms();
     grid->h = g;
     *out = grid;
     return CUTE_OK;
@@ -464,7 +467,6 @@ extern "C" void cute_free_grid(cute_grid* g) {
     dfree(g->h.p32, nullptr);
     dfree(g->h.p64, nullptr);
     dfree(g->h.cstart, nullptr);
-    (void)hipStreamSynchronize(nullptr);
     delete g;
 }
 

@@ -59,13 +59,21 @@ struct EventTimer {
         if (hipEventCreate(&b) != hipSuccess) b = nullptr;
         if (a) (void)hipEventRecord(a, s);
     }
-    double stop_ms() {
+    // record the end (no wait)
+    void stop() {
+        if (a && b) (void)hipEventRecord(b, s);
+    }
+    // time between the two records, waiting for the end if needed
+    double elapsed_ms() {
         if (!a || !b) return 0.0;
-        (void)hipEventRecord(b, s);
         (void)hipEventSynchronize(b);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, a, b);
         return ms;
+    }
+    double stop_ms() {
+        stop();
+        return elapsed_ms();
     }
     ~EventTimer() {
         if (a) (void)hipEventDestroy(a);

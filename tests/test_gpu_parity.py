@@ -288,9 +288,15 @@ def test_tuned_cell_size_counts_match_oracle():
     assert best in times and all(np.isfinite(v) and v > 0 for v in times.values())
     got = gpu_counts(d, None, bn, cute.PREC_FP32_EDGE, cute.GEOM_BOX_OPEN, r_max=40.0, cell=best)
     np.testing.assert_array_equal(got, oracle.count_pairs(d, None, obin(cute.BIN_RMU, re_, me)))
-    # explicit candidates, one of them too coarse for a periodic box of side 100
+    # explicit candidates in a periodic box (the grid keeps enough cells per
+    # side whatever the requested side, so every candidate is usable here)
     u = catalogs.uniform_box(3000, 100.0, seed=5)
-    mb = cute.Binning(cute.BIN_MONO, np.linspace(0, 20, 11))
-    best, times = cute.tune_cell_size(u, cute.GEOM_BOX_PERIODIC, mb, box_size=100.0,
+    e = np.linspace(0, 20, 11)
+    mb = cute.Binning(cute.BIN_MONO, e)
+    best, times = cute.tune_cell_size(u, cute.GEOM_BOX_PERIODIC, mb, box_size=100.0, r_max=20.0,
                                       candidates=[5.0, 10.0, 60.0])
-    assert best in (5.0, 10.0) and math.isnan(times[60.0])
+    assert best in (5.0, 10.0, 60.0) and set(times) == {5.0, 10.0, 60.0}
+    got = gpu_counts(u, None, mb, cute.PREC_FP32_EDGE, cute.GEOM_BOX_PERIODIC, L=100.0, r_max=20.0,
+                     cell=best)
+    np.testing.assert_array_equal(got, oracle.count_pairs(u, None, obin(cute.BIN_MONO, e,
+                                                                         periodic=True, L=100.0)))

@@ -257,7 +257,9 @@ __device__ __forceinline__ uint32_t c32_bin(const CountArgs& P, const C32& c) {
     return __umul24(c.kb, (uint32_t)P.n2p1) + (c.kmb - kBias);
 }
 
-template <int MODE, int EST, bool WANT_TENT>
+// LO: the first threshold can be crossed (out_lo >= 0); without it a pair is
+// never clean-out on the low side, so that compare is skipped.
+template <int MODE, int EST, bool WANT_TENT, bool LO = true>
 __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, float dx, float dy,
                                           float dz, float lx, float ly, float lz, uint32_t* tent) {
     C32 c;
@@ -277,7 +279,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         c.kb = est_bits(ts, P.e1a, T, P.top1);
         float2 b = band_at(T.tb1, c.kb);
         c.in = (v >= b.x) & (v < b.y);
-        c.out = (v >= P.out_hi) | (v < P.out_lo);
+        c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);
         if (WANT_TENT) *tent = (v >= P.bot32 & v < P.top32) ? c.kb - kBias : kNoBin;
         return c;
     }
@@ -299,7 +301,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         c.in = rin & min_;
         // only r decides a clean "out"; a pair outside a partial mu range is
         // re-tested instead (never the case for mu in [0, 1])
-        c.out = (v >= P.out_hi) | (v < P.out_lo);
+        c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);
         if (WANT_TENT) {
             bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;
@@ -329,7 +331,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         bool rin = (v >= b.x) & (v < b.y);
         bool min_ = (flo >= delta) & (fhi <= -delta);
         c.in = rin & min_;
-        c.out = (v >= P.out_hi) | (v < P.out_lo);
+        c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);
         if (WANT_TENT) {
             bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;
@@ -512,7 +514,7 @@ __device__ __forceinline__ void home_valid(const CountArgs& P, uint32_t h, bool*
     }
 }
 
-template <int MODE, int PREC, int EST, bool PM, bool MASKED, uint32_t U>
+template <int MODE, int PREC, int EST, bool PM, bool MASKED, bool LO, uint32_t U>
 __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const Tab32& T,
                                        const float2* B1, const float2* B2, const double* T1,
                                        const double* T2, int lane, bool lvalid, bool lmask,
@@ -547,7 +549,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
             off[u] = __umul24(tent, (uint32_t)P.hs2) + lb;
             amb[u] = false;
         } else {
-            const C32 c = classify32<MODE, EST, false>(P, T, dx, dy, dz, lx, ly, lz, nullptr);
+            const C32 c = classify32<MODE, EST, false, LO>(P, T, dx, dy, dz, lx, ly, lz, nullptr);
             cnt[u] = act & c.in;
             amb[u] = act & !(c.in | c.out);
             // LDS byte address of the bin in this lane's copy of the histogram
@@ -703,17 +705,25 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
             qly = qy + P.lcy;
             qlz = qz + P.lcz;
         }
-#define CUTE_RUN32(MSK)                                                                            \
+#define CUTE_RUN32(MSK, LOW)                                                                     \
     {                                                                                              \
         uint32_t h = ts;                                                                           \
         for (; h + U <= te; h += U)                                                                \
-            step32<MODE, PREC, EST, PM, MSK, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid, C.lmask,  \
-                                                C.lj, C.lcode, qx, qy, qz, qlx, qly, qlz, lb, h);  \
+            step32<MODE, PREC, EST, PM, MSK, LOW, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
+                                                     C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
+                                                     qlz, lb, h);                                  \
         for (; h < te; h++)                                                                        \
-            step32<MODE, PREC, EST, PM, MSK, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid, C.lmask,  \
-                                                C.lj, C.lcode, qx, qy, qz, qlx, qly, qlz, lb, h);  \
+            step32<MODE, PREC, EST, PM, MSK, LOW, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
+                                                     C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
+                                                     qlz, lb, h);                                  \
     }
-        if (C.masked) CUTE_RUN32(true) else CUTE_RUN32(false)
+        // bins starting at zero separation have no low-side clean "out"
+        const bool low = !(P.out_lo < 0.0f) || MODE == M_SIGMAPI;
+        if (C.masked) {
+            if (low) CUTE_RUN32(true, true) else CUTE_RUN32(true, false)
+        } else {
+            if (low) CUTE_RUN32(false, true) else CUTE_RUN32(false, false)
+        }
 #undef CUTE_RUN32
     }
     C.filled = 0;

@@ -249,12 +249,12 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
                                                    uint32_t* __restrict__ rank,
                                                    uint32_t* __restrict__ hist) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
+    const bool live = t < ntiles;
+    const Tile tl = live ? tiles[t] : Tile{0u, 0u, 0u, 0u};
     const int c0 = (int)(tl.c0c1 & 0xffffu), c1 = (int)(tl.c0c1 >> 16);
     const int cy = (int)(tl.row % (uint32_t)any), cz = (int)(tl.row / (uint32_t)any);
     uint64_t nb = 0, rows = 0;
-    for (int e = 0; e < nst; e++) {
+    for (int e = 0; live && e < nst; e++) {
         const int4 o = st[e];
         int by = cy + o.x, bz = cz + o.y;
         const bool same = is_auto && o.x == 0 && o.y == 0;
@@ -284,8 +284,21 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
     const uint64_t c = (uint64_t)(tl.end - tl.start) * nb + 128ull * rows + 2048ull;
     const float lc = (__builtin_amdgcn_logf((float)c) - 11.0f) * 8.0f;
     const uint32_t b = kCostBuckets - 1u - (uint32_t)fminf(fmaxf(lc, 0.0f), (float)(kCostBuckets - 1));
-    key[t] = b;
-    rank[t] = atomicAdd(&hist[b], 1u);
+    // (a thread past the end joins the barriers and counts nothing)
+    // rank within the bucket: LDS atomics inside the block, then one global
+    // atomic per (block, bucket) reserves the block's range
+    __shared__ uint32_t lh[kCostBuckets], lbase[kCostBuckets];
+    for (uint32_t i = threadIdx.x; i < kCostBuckets; i += blockDim.x) lh[i] = 0u;
+    __syncthreads();
+    const uint32_t lr = live ? atomicAdd(&lh[b], 1u) : 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kCostBuckets; i += blockDim.x)
+        if (lh[i]) lbase[i] = atomicAdd(&hist[i], lh[i]);
+    __syncthreads();
+    if (live) {
+        key[t] = b;
+        rank[t] = lbase[b] + lr;
+    }
 }
 
 // Scatter the tiles into bucket order: every block scans the bucket counts in

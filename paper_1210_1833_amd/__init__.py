@@ -141,14 +141,21 @@ def _check(rc: int):
                                          lib.cute_last_error().decode()))
 
 
+_torch_gpu = None
+
+
 def _stream_handle(stream):
+    """The HIP stream to run on: the given one, or torch's current stream."""
+    global _torch_gpu
     if stream is None:
-        try:
-            import torch
-            if torch.cuda.is_available():
-                return torch.cuda.current_stream().cuda_stream
-        except Exception:  # pragma: no cover - torch without ROCm
-            pass
+        if _torch_gpu is None:
+            try:
+                import torch
+                _torch_gpu = torch if torch.cuda.is_available() else False
+            except Exception:  # pragma: no cover - torch without ROCm
+                _torch_gpu = False
+        if _torch_gpu:
+            return _torch_gpu.cuda.current_stream().cuda_stream
         return None
     if isinstance(stream, int):
         return stream
@@ -162,6 +169,11 @@ class Binning:
     edges1: np.ndarray
     edges2: np.ndarray | None = None
     los: int = LOS_Z
+
+    def __setattr__(self, name, value):
+        if name != "_c":
+            object.__setattr__(self, "_c", None)  # the C struct is rebuilt on next use
+        object.__setattr__(self, name, value)
 
     def __post_init__(self):
         self.edges1 = np.ascontiguousarray(self.edges1, dtype=np.float64)
@@ -178,6 +190,11 @@ class Binning:
         return int(np.prod(self.shape))
 
     def c(self) -> CBinning:
+        """The C struct (kept: it points into edges1/edges2, which must not be
+        replaced afterwards)."""
+        cached = getattr(self, "_c", None)
+        if cached is not None:
+            return cached
         b = CBinning()
         b.kind, b.los = int(self.kind), int(self.los)
         b.n1 = len(self.edges1) - 1
@@ -188,6 +205,7 @@ class Binning:
         else:
             b.n2 = len(self.edges2) - 1
             b.edges2 = self.edges2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._c = b
         return b
 
 

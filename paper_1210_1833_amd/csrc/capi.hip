@@ -113,15 +113,15 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     TempList tmp(hs);
     unsigned char* blob = nullptr;
     if ((s = tmp.alloc(&blob, total)) != CUTE_OK) return s;
-    std::vector<unsigned char> hb(oAR);
+    // tables and zeroed counts in one copy (the argument block follows later)
+    std::vector<unsigned char> hb(total, 0);
     memcpy(hb.data() + oT1, pl.T1.data(), pl.T1.size() * 8);
     memcpy(hb.data() + oT2, pl.T2.data(), pl.T2.size() * 8);
     memcpy(hb.data() + oB1, pl.band1.data(), pl.band1.size() * 8);
     memcpy(hb.data() + oB2, pl.band2.data(), pl.band2.size() * 8);
     if (!geo.stencil.empty())
         memcpy(hb.data() + oST, geo.stencil.data(), geo.stencil.size() * sizeof(int4));
-    CUTE_HIP(hipMemcpyAsync(blob, hb.data(), oAR, hipMemcpyHostToDevice, hs));
-    CUTE_HIP(hipMemsetAsync(blob + oWK, 0, ((size_t)nbins + 5) * 8, hs));
+    CUTE_HIP(hipMemcpyAsync(blob, hb.data(), total, hipMemcpyHostToDevice, hs));
     unsigned long long* work = reinterpret_cast<unsigned long long*>(blob + oWK);
     CountArgs* dargs = reinterpret_cast<CountArgs*>(blob + oAR);
     const int4* dst = geo.stencil.empty() ? nullptr : reinterpret_cast<const int4*>(blob + oST);

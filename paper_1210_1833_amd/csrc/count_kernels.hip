@@ -176,6 +176,7 @@ cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int
 __global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict__ cstart, int nx,
                                                      int nrows, int max_w, uint32_t* __restrict__ ntile) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) ntile[nrows] = 0u;  // the scan's last entry becomes the total
     if (r >= nrows) return;
     const uint32_t* cs = cstart + (size_t)r * nx;
     uint32_t cnt = 0, fill = 0;
@@ -370,7 +371,6 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     const unsigned nb = (unsigned)((nrows + 255) / 256);
     hipLaunchKernelGGL(k_tiles_count, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows, max_w, cnt);
     CUTE_HIP(hipGetLastError());
-    CUTE_HIP(hipMemsetAsync(cnt + nrows, 0, sizeof(uint32_t), s));
     if ((st = exclusive_scan(cnt, cnt, (size_t)nrows + 1, s)) != CUTE_OK) return st;
     uint32_t total = 0;
     CUTE_HIP(hipMemcpyAsync(&total, cnt + nrows, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

@@ -145,6 +145,7 @@ struct GridHost {
     float4* p32;
     P64* p64;
     uint32_t* cstart;
+    void* block;         // the one device allocation holding p64, p32 and cstart
     double ms_build;
     GridView view() const;
 };

@@ -420,19 +420,23 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
     cute_grid* grid = new (std::nothrow) cute_grid;
     if (!grid) return fail(CUTE_E_OUT_OF_MEMORY, "host allocation");
     auto cleanup = [&](cute_status e) {
-        dfree(g.p32, s);
-        dfree(g.p64, s);
-        dfree(g.cstart, s);
+        dfree(g.block, s);
         delete grid;
         return e;
     };
-    if ((st = dalloc(&g.p32, n, s)) != CUTE_OK) return cleanup(st);
-    if ((st = dalloc(&g.p64, n, s)) != CUTE_OK) return cleanup(st);
-    if ((st = dalloc(&g.cstart, ncells + 1, s)) != CUTE_OK) return cleanup(st);
+    // one block per grid: [p64 (32 B per point) | p32 (16 B) | cstart]
+    unsigned char* blk = nullptr;
+    const size_t b64 = (size_t)n * sizeof(P64), b32 = (size_t)n * sizeof(float4);
+    if ((st = dalloc(&blk, b64 + b32 + ((size_t)ncells + 1) * sizeof(uint32_t), s)) != CUTE_OK)
+        return cleanup(st);
+    g.block = blk;
+    g.p64 = reinterpret_cast<P64*>(blk);
+    g.p32 = reinterpret_cast<float4*>(blk + b64);
+    g.cstart = reinterpret_cast<uint32_t*>(blk + b64 + b32);
 
-    uint32_t *key = nullptr, *rank = nullptr;
-    if ((st = tmp.alloc(&key, n)) != CUTE_OK) return cleanup(st);
-    if ((st = tmp.alloc(&rank, n)) != CUTE_OK) return cleanup(st);
+    uint32_t* key = nullptr;  // keys and ranks in one temporary
+    if ((st = tmp.alloc(&key, 2 * (size_t)n)) != CUTE_OK) return cleanup(st);
+    uint32_t* rank = key + n;
     if (hipMemsetAsync(g.cstart, 0, (ncells + 1) * sizeof(uint32_t), s) != hipSuccess)
         return cleanup(fail(CUTE_E_DEVICE, "hipMemsetAsync"));
     CellGeo cg{(int)g.geom, g.nx, g.ny, g.nz, g.ox, g.oy, g.oz, g.ax, g.ay, g.az, g.L};
@@ -464,9 +468,7 @@ extern "C" void cute_free_grid(cute_grid* g) {
     if (!g) return;
     // the buffers come from the stream-ordered pool; the caller guarantees
     // that no work on any stream still uses the grid
-    dfree(g->h.p32, nullptr);
-    dfree(g->h.p64, nullptr);
-    dfree(g->h.cstart, nullptr);
+    dfree(g->h.block, nullptr);
     delete g;
 }
 

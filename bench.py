@@ -73,13 +73,34 @@ def batched_leg(cute, torch, dev, runs=1):
     mono = cute.Binning(cute.BIN_MONO, np.arange(31) * 5.0)
     rmu = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(51) / 50.0, los=cute.LOS_Z)
 
-    def dgrid(cat):
-        xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (cat.x, cat.y, cat.z)]
-        return cute.build_grid(xyz, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0)
+    def dxyz(cat):
+        return [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (cat.x, cat.y, cat.z)]
+
+    # grid layout (cell side, tile size) from the tuner: on the smallest, the
+    # median and the largest mock (each mock takes the choice of the nearest
+    # size on a log scale) and on the jackknife base
+    t0 = time.perf_counter()
+    sizes = np.array([len(m) for m in mocks])
+    reps = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
+    tuned = {}
+    for k in reps:
+        c, t, _ = cute.tune_grid(dxyz(mocks[k]), cute.GEOM_BOX_PERIODIC, rmu, box_size=L, r_max=200.0)
+        tuned[k] = (c, t)
+    cb, tb, _ = cute.tune_grid(dxyz(base), cute.GEOM_BOX_PERIODIC, rmu, box_size=L, r_max=200.0)
+    t_tune = time.perf_counter() - t0
+
+    def layout(n):
+        k = min(reps, key=lambda r: abs(np.log(sizes[r]) - np.log(n)))
+        return tuned[k]
 
     t0 = time.perf_counter()
-    gm = [dgrid(m) for m in mocks]
-    gb = dgrid(base)
+    gm = []
+    for m in mocks:
+        c, t = layout(len(m))
+        gm.append(cute.build_grid(dxyz(m), cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0,
+                                  cell_size=c, tile_points=t))
+    gb = cute.build_grid(dxyz(base), cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0,
+                         cell_size=cb, tile_points=tb)
     torch.cuda.synchronize()
     t_grid = time.perf_counter() - t0
     reg = torch.from_numpy(region).to(dev)
@@ -125,7 +146,11 @@ def batched_leg(cute, torch, dev, runs=1):
             "pair_evals": int(st["pair_evals"]), "pairs_in_range": int(st["pairs_in_range"]),
             "gpair_evals_per_s": round(st["pair_evals"] / (ms * 1e-3) / 1e9, 3),
             "retests": int(st["retests"]), "spot_checks_bit_exact_vs_fp64_single": ok,
-            "host_s": {"generate": round(t_gen, 2), "grids": round(t_grid, 2), "plan": round(t_plan, 2)}}
+            "tuned_layout": {"mocks": {str(int(sizes[k])): {"cell": round(c, 3), "tile": t}
+                                       for k, (c, t) in tuned.items()},
+                             "jackknife_base": {"cell": round(cb, 3), "tile": tb}},
+            "host_s": {"generate": round(t_gen, 2), "tune": round(t_tune, 2),
+                       "grids": round(t_grid, 2), "plan": round(t_plan, 2)}}
 
 
 def committed_traffic():
@@ -287,19 +312,20 @@ def main():
 
 
 def tuned_leg(cute, xyz, bn, counts, c32):
-    """cute_tune_cell_size on the benchmark data, then the count with its choice."""
-    best, cand = cute.tune_cell_size(xyz, cute.GEOM_BOX_OPEN, bn, r_max=200.0)
-    gt = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0, cell_size=best)
+    """cute_tune_grid on the benchmark data, then the count with its choice."""
+    cell, tile, cand = cute.tune_grid(xyz, cute.GEOM_BOX_OPEN, bn, r_max=200.0)
+    gt = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0, cell_size=cell, tile_points=tile)
     tt = []
     for _ in range(5):
         _, stt = cute.count_pairs(gt, None, bn, cute.PREC_FP32_EDGE, out=counts, with_stats=True)
         tt.append(stt["ms_count"])
     gt.close()
     tuned_ok = bool(np.array_equal(counts.cpu().numpy().astype(np.uint64), c32))
-    return {"cell_size": best if best > 0 else "auto", "kernel_ms": round(min(tt), 4),
-            "pair_evals": int(stt["pair_evals"]), "bit_exact": tuned_ok,
-            "candidates_ms": {("auto" if k == 0 else round(k, 3)): round(v, 4)
-                              for k, v in cand.items()}}
+    return {"cell_size": cell if cell > 0 else "auto", "tile_points": tile,
+            "kernel_ms": round(min(tt), 4), "pair_evals": int(stt["pair_evals"]),
+            "bit_exact": tuned_ok,
+            "candidates_ms": {"%s/%d" % ("auto" if c == 0 else round(c, 3), t): round(v, 4)
+                              for (c, t), v in cand.items()}}
 
 
 if __name__ == "__main__":

@@ -102,6 +102,8 @@ typedef struct {
     double cell_size;  /* cell side (pixel side in radians for SPHERE);
                           0 = chosen by the library                           */
     int32_t device_ptrs; /* nonzero: x, y, z are device pointers             */
+    int32_t tile_points; /* most points in one home tile when this grid is the
+                            first argument of a count, 1..64; 0 = 64         */
 } cute_grid_params;
 
 typedef struct {
@@ -164,25 +166,29 @@ cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);
 
-/* Choose the cell side of the cell list of Sec. 3.3 by measurement. The best
- * side is data dependent (Sec. 3.3), so each candidate side is timed: a grid
- * of n points (x, y, z, read as for
- * cute_build_grid with parameters p, cell_size ignored) is built with it and
- * the autocorrelation under bins is counted (every 8th home tile for
- * catalogs above 4e5 points), twice, keeping the faster run.
- * candidates: n_cand sides (0 = the library's density rule); n_cand == 0
- *   uses {0, r/2, r/3, r/4, r/5, r/6} with r the binning's reach (theta in
+/* Choose the cell side and the home-tile size of a grid by measurement. The
+ * best cell side is data dependent (Sec. 3.3), so each candidate pair is
+ * timed: a grid of n points (x, y, z, read as for cute_build_grid with
+ * parameters p, cell_size and tile_points ignored) is built with it and the
+ * autocorrelation under bins is counted (an evenly spread sample of about
+ * 32768 home tiles when there are more, enough for several per wave, its
+ * time scaled by the sampled share of the tiles), twice, keeping the faster
+ * run.
+ * cells: n_cell sides (0 = the library's density rule); n_cell == 0 uses
+ *   {0, r/2, r/3, r/4, r/5, r/6} with r the binning's reach (theta in
  *   radians for SPHERE).
- * best: the fastest candidate. ms (nullable): the time of each candidate
- *   (n_cand entries, 6 for the default set; NaN for a side the geometry
- *   rejects, e.g. too coarse for a periodic box).
+ * tiles: n_tile tile sizes in 1..64; n_tile == 0 uses {32, 64}.
+ * best_cell, best_tile: the fastest pair. ms (nullable): the time of each
+ *   pair, cell-major (n_cell x n_tile entries with the defaults' counts when
+ *   0 is given; NaN for a pair the geometry rejects).
  * Errors: those of cute_build_grid and cute_count_pairs; CUTE_E_INVALID_ARG
- * for n_cand outside [0, 64], negative candidates or when no candidate is
- * usable. */
-cute_status cute_tune_cell_size(const double* x, const double* y, const double* z, int64_t n,
-                                const cute_grid_params* p, const cute_binning* bins,
-                                cute_precision prec, int32_t n_cand, const double* candidates,
-                                void* stream, double* best, double* ms);
+ * for NULL outputs, n_cell or n_tile outside [0, 64], negative sides, tile
+ * sizes outside 1..64, or when no pair is usable. */
+cute_status cute_tune_grid(const double* x, const double* y, const double* z, int64_t n,
+                           const cute_grid_params* p, const cute_binning* bins,
+                           cute_precision prec, int32_t n_cell, const double* cells,
+                           int32_t n_tile, const int32_t* tiles, void* stream, double* best_cell,
+                           int32_t* best_tile, double* ms);
 
 /* ---- Batched counts ---------------------------------------------------------
  * The error analyses of Sec. 4 (Fig. 5) need the same pair counts over many

@@ -27,7 +27,7 @@ EST_NATURAL, EST_LS, EST_BOX = range(3)
 BATCH_GRAPH, BATCH_EAGER = range(2)
 
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
-            "cute_tune_cell_size", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
+            "cute_tune_grid", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
@@ -41,7 +41,7 @@ class CuteError(RuntimeError):
 class GridParams(ctypes.Structure):
     _fields_ = [("geom", ctypes.c_int), ("box_size", ctypes.c_double),
                 ("r_max", ctypes.c_double), ("cell_size", ctypes.c_double),
-                ("device_ptrs", ctypes.c_int32)]
+                ("device_ptrs", ctypes.c_int32), ("tile_points", ctypes.c_int32)]
 
 
 class CBinning(ctypes.Structure):
@@ -98,10 +98,11 @@ def load():
     lib.cute_count_pairs.restype = ctypes.c_int
     lib.cute_count_pairs.argtypes = [vp, vp, ctypes.POINTER(CBinning), ctypes.c_int, vp,
                                      ctypes.c_int32, ctypes.POINTER(CountStats), vp]
-    lib.cute_tune_cell_size.restype = ctypes.c_int
-    lib.cute_tune_cell_size.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(GridParams),
-                                        ctypes.POINTER(CBinning), ctypes.c_int, ctypes.c_int32, dp,
-                                        vp, dp, dp]
+    lib.cute_tune_grid.restype = ctypes.c_int
+    lib.cute_tune_grid.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(GridParams),
+                                   ctypes.POINTER(CBinning), ctypes.c_int, ctypes.c_int32, dp,
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, dp,
+                                   ctypes.POINTER(ctypes.c_int32), dp]
     ip = ctypes.POINTER(ctypes.c_int64)
     lib.cute_batch_create.restype = ctypes.c_int
     lib.cute_batch_create.argtypes = [ctypes.POINTER(CBatchItem), ctypes.c_int32, ctypes.c_int, vp,
@@ -267,40 +268,54 @@ def _coords(pos):
 
 
 def build_grid(pos, geom: int, box_size: float = 0.0, r_max: float = 0.0,
-               cell_size: float = 0.0, stream=None) -> Grid:
+               cell_size: float = 0.0, stream=None, tile_points: int = 0) -> Grid:
     """cute_build_grid. ``pos``: (n, 3) float64 numpy/torch (host or device),
     a (x, y, z) triple of tensors, or an object with x, y, z arrays."""
     lib = load()
     x, y, z, n, dev, keep = _coords(pos)
-    p = GridParams(int(geom), float(box_size), float(r_max), float(cell_size), int(dev))
+    p = GridParams(int(geom), float(box_size), float(r_max), float(cell_size), int(dev),
+                   int(tile_points))
     h = ctypes.c_void_p()
     _check(lib.cute_build_grid(x, y, z, int(n), ctypes.byref(p), _stream_handle(stream),
                                ctypes.byref(h)))
     return Grid(h, int(n), keep if dev else None)
 
 
-def tune_cell_size(pos, geom: int, binning: Binning, box_size: float = 0.0, r_max: float = 0.0,
-                   prec: int = PREC_FP32_EDGE, candidates=None, stream=None):
-    """cute_tune_cell_size: (best cell side, {candidate: ms}) for the
-    autocorrelation of ``pos`` under ``binning`` (0 = the library's rule)."""
+def tune_grid(pos, geom: int, binning: Binning, box_size: float = 0.0, r_max: float = 0.0,
+              prec: int = PREC_FP32_EDGE, cells=None, tiles=None, stream=None):
+    """cute_tune_grid: (best cell side, best tile size, {(cell, tile): ms}) for
+    the autocorrelation of ``pos`` under ``binning`` (cell 0 = the library's
+    density rule). Build the grid with ``cell_size`` and ``tile_points`` set
+    to the returned values."""
     lib = load()
     x, y, z, n, dev, keep = _coords(pos)
-    p = GridParams(int(geom), float(box_size), float(r_max), 0.0, int(dev))
+    p = GridParams(int(geom), float(box_size), float(r_max), 0.0, int(dev), 0)
     cb = binning.c()
-    cand = None if candidates is None else np.ascontiguousarray(candidates, dtype=np.float64)
-    nc = 0 if cand is None else len(cand)
-    ms = np.full(6 if nc == 0 else nc, np.nan)
-    best = ctypes.c_double()
     dp = ctypes.POINTER(ctypes.c_double)
-    _check(lib.cute_tune_cell_size(x, y, z, int(n), ctypes.byref(p), ctypes.byref(cb), int(prec), nc,
-                                   None if cand is None else cand.ctypes.data_as(dp),
-                                   _stream_handle(stream), ctypes.byref(best), ms.ctypes.data_as(dp)))
-    if cand is None:
+    if cells is None:
         r = binning.edges1[-1] if binning.kind == BIN_THETA else (
             float(np.hypot(binning.edges1[-1], binning.edges2[-1])) if binning.kind == BIN_SIGMAPI
-            else binning.edges1[-1])
-        cand = np.array([0.0] + [r / k for k in (2, 3, 4, 5, 6)])
-    return best.value, dict(zip([float(c) for c in cand], [float(m) for m in ms]))
+            else float(binning.edges1[-1]))
+        cl, ca = [0.0] + [r / k for k in (2, 3, 4, 5, 6)], None
+    else:
+        ca = np.ascontiguousarray(cells, dtype=np.float64)
+        cl = [float(c) for c in ca]
+    if tiles is None:
+        tl, ta = [32, 64], None
+    else:
+        ta = np.ascontiguousarray(tiles, dtype=np.int32)
+        tl = [int(t) for t in ta]
+    ms = np.full(len(cl) * len(tl), np.nan)
+    bc, bt = ctypes.c_double(), ctypes.c_int32()
+    _check(lib.cute_tune_grid(x, y, z, int(n), ctypes.byref(p), ctypes.byref(cb), int(prec),
+                              0 if ca is None else len(ca),
+                              None if ca is None else ca.ctypes.data_as(dp),
+                              0 if ta is None else len(ta),
+                              None if ta is None else ta.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              _stream_handle(stream), ctypes.byref(bc), ctypes.byref(bt),
+                              ms.ctypes.data_as(dp)))
+    times = {(c, t): float(ms[i * len(tl) + j]) for i, c in enumerate(cl) for j, t in enumerate(tl)}
+    return bc.value, bt.value, times
 
 
 def count_pairs(a: Grid, b: Grid | None, binning: Binning, prec: int = PREC_FP32_EDGE,

@@ -69,11 +69,12 @@ extern "C" const char* cute_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-// One pair count; with tile_stride > 1 only every tile_stride-th home tile is
-// counted (the cell-size tuner's sample).
+// One pair count; with max_tiles > 0 only an evenly spread sample of about
+// max_tiles home tiles is counted (the tuner's sample).
 cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binning* bins,
                        cute_precision prec, uint64_t* counts, int32_t counts_on_device,
-                       cute_count_stats* st, void* stream, int tile_stride) {
+                       cute_count_stats* st, void* stream, uint32_t max_tiles,
+                       double* sampled_share = nullptr) {
     if (!ga) return fail(CUTE_E_INVALID_ARG, "grid a is NULL");
     if (!counts) return fail(CUTE_E_INVALID_ARG, "counts is NULL");
     cute_status s = validate_binning(bins);
@@ -145,6 +146,7 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
         dfree(tiles, hs);
         return s;
     }
+    const uint32_t tile_stride = max_tiles > 0 ? (ntiles + max_tiles - 1) / max_tiles : 1;
     if (tile_stride > 1 && ntiles > 0) {
         // keep every tile_stride-th tile (in place: a stream-ordered round trip)
         std::vector<Tile> h(ntiles);
@@ -155,7 +157,8 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
             return hip_status(e, "tile sample");
         }
         uint32_t k = 0;
-        for (uint32_t t = 0; t < ntiles; t += (uint32_t)tile_stride) h[k++] = h[t];
+        for (uint32_t t = 0; t < ntiles; t += tile_stride) h[k++] = h[t];
+        if (sampled_share) *sampled_share = (double)k / (double)ntiles;
         ntiles = k;
         e = hipMemcpyAsync(tiles, h.data(), ntiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
@@ -211,41 +214,57 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
                                         const cute_binning* bins, cute_precision prec,
                                         uint64_t* counts, int32_t counts_on_device,
                                         cute_count_stats* st, void* stream) {
-    return count_impl(ga, gb, bins, prec, counts, counts_on_device, st, stream, 1);
+    return count_impl(ga, gb, bins, prec, counts, counts_on_device, st, stream, 0);
 }
 
-extern "C" cute_status cute_tune_cell_size(const double* x, const double* y, const double* z,
-                                           int64_t n, const cute_grid_params* p,
-                                           const cute_binning* bins, cute_precision prec,
-                                           int32_t n_cand, const double* candidates,
-                                           void* stream, double* best, double* ms) {
-    if (!best) return fail(CUTE_E_INVALID_ARG, "best is NULL");
+extern "C" cute_status cute_tune_grid(const double* x, const double* y, const double* z,
+                                      int64_t n, const cute_grid_params* p,
+                                      const cute_binning* bins, cute_precision prec,
+                                      int32_t n_cell, const double* cells, int32_t n_tile,
+                                      const int32_t* tiles, void* stream, double* best_cell,
+                                      int32_t* best_tile, double* ms) {
+    if (!best_cell || !best_tile) return fail(CUTE_E_INVALID_ARG, "best_cell or best_tile is NULL");
     if (!p) return fail(CUTE_E_INVALID_ARG, "params is NULL");
     cute_status s = validate_binning(bins);
     if (s != CUTE_OK) return s;
-    if (n_cand < 0 || n_cand > 64 || (n_cand > 0 && !candidates))
-        return fail(CUTE_E_INVALID_ARG, "n_cand must be in [0, 64] with candidates given");
+    if (n_cell < 0 || n_cell > 64 || (n_cell > 0 && !cells) || n_tile < 0 || n_tile > 64 ||
+        (n_tile > 0 && !tiles))
+        return fail(CUTE_E_INVALID_ARG, "n_cell and n_tile must be in [0, 64] with arrays given");
     Plan pl;
     plan_binning(bins, pl);
     const double rmax = bins->kind == CUTE_BIN_THETA ? bins->edges1[bins->n1] : pl.rmax;
     std::vector<double> cand;
-    if (n_cand > 0) {
-        for (int i = 0; i < n_cand; i++) {
-            if (!(candidates[i] >= 0.0) || !std::isfinite(candidates[i]))
-                return fail(CUTE_E_INVALID_ARG, "candidates must be finite and >= 0");
-            cand.push_back(candidates[i]);
+    if (n_cell > 0) {
+        for (int i = 0; i < n_cell; i++) {
+            if (!(cells[i] >= 0.0) || !std::isfinite(cells[i]))
+                return fail(CUTE_E_INVALID_ARG, "cell sides must be finite and >= 0");
+            cand.push_back(cells[i]);
         }
     } else {
         cand.push_back(0.0);  // the library's density rule
         for (double f : {1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6}) cand.push_back(rmax * f);
     }
-    const int stride = n > 400000 ? 8 : 1;  // sample large catalogs
+    std::vector<int> tsz;
+    if (n_tile > 0) {
+        for (int i = 0; i < n_tile; i++) {
+            if (tiles[i] < 1 || tiles[i] > 64)
+                return fail(CUTE_E_INVALID_ARG, "tile sizes must be in 1..64");
+            tsz.push_back(tiles[i]);
+        }
+    } else {
+        tsz = {32, 64};
+    }
+    // a sample of home tiles (longest-first order, evenly spread), large
+    // enough that the persistent waves take several each: the time then
+    // tracks throughput, not the longest single tile
+    const uint32_t sample = 32768;
     std::vector<uint64_t> counts((size_t)pl.a.nbins);
     double best_ms = INFINITY;
     int best_i = -1;
-    for (size_t i = 0; i < cand.size(); i++) {
+    for (size_t i = 0; i < cand.size() * tsz.size(); i++) {
         cute_grid_params q = *p;
-        q.cell_size = cand[i];
+        q.cell_size = cand[i / tsz.size()];
+        q.tile_points = tsz[i % tsz.size()];
         if (q.r_max < rmax) q.r_max = rmax;
         cute_grid* g = nullptr;
         s = cute_build_grid(x, y, z, n, &q, stream, &g);
@@ -253,20 +272,23 @@ extern "C" cute_status cute_tune_cell_size(const double* x, const double* y, con
         if (s == CUTE_OK) {
             for (int rep = 0; rep < 2 && s == CUTE_OK; rep++) {
                 cute_count_stats st;
-                s = count_impl(g, nullptr, bins, prec, counts.data(), 0, &st, stream, stride);
-                if (s == CUTE_OK) t = std::min(t, st.ms_count);
+                double share = 1.0;  // the time is scaled to the whole count
+                s = count_impl(g, nullptr, bins, prec, counts.data(), 0, &st, stream, sample,
+                               &share);
+                if (s == CUTE_OK) t = std::min(t, st.ms_count / share);
             }
             cute_free_grid(g);
         }
         if (s == CUTE_E_OUT_OF_MEMORY || s == CUTE_E_DEVICE) return s;
-        if (ms) ms[i] = s == CUTE_OK ? t : NAN;  // a rejected candidate (too coarse) is NaN
+        if (ms) ms[i] = s == CUTE_OK ? t : NAN;  // a rejected pair is NaN
         if (s == CUTE_OK && t < best_ms) {
             best_ms = t;
             best_i = (int)i;
         }
     }
-    if (best_i < 0) return fail(CUTE_E_INVALID_ARG, "no candidate cell size is usable");
-    *best = cand[best_i];
+    if (best_i < 0) return fail(CUTE_E_INVALID_ARG, "no candidate is usable");
+    *best_cell = cand[best_i / tsz.size()];
+    *best_tile = tsz[best_i % tsz.size()];
     return CUTE_OK;
 }
 

@@ -169,12 +169,13 @@ cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int
     }
 }
 
-// Home tiles: each row of cells is cut into runs of at most kTileMax points
+// Home tiles: each row of cells is cut into runs of at most tmax points
 // whose x-extent stays within max_w cells (so that periodic stencils never
 // wrap onto themselves); a cell with more points is split. One thread walks
 // one row.
 __global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict__ cstart, int nx,
-                                                     int nrows, int max_w, uint32_t* __restrict__ ntile) {
+                                                     int nrows, int max_w, uint32_t tmax,
+                                                     uint32_t* __restrict__ ntile) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r == 0) ntile[nrows] = 0u;  // the scan's last entry becomes the total
     if (r >= nrows) return;
@@ -184,12 +185,12 @@ __global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict_
     for (int c = 0; c < nx; c++) {
         uint32_t left = cs[c + 1] - cs[c];
         while (left > 0) {
-            if (fill == 0 || fill == kTileMax || c - first + 1 > max_w) {
+            if (fill == 0 || fill == tmax || c - first + 1 > max_w) {
                 cnt++;
                 fill = 0;
                 first = c;
             }
-            uint32_t take = kTileMax - fill < left ? kTileMax - fill : left;
+            uint32_t take = tmax - fill < left ? tmax - fill : left;
             fill += take;
             left -= take;
         }
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict_
 }
 
 __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict__ cstart, int nx,
-                                                     int nrows, int max_w,
+                                                     int nrows, int max_w, uint32_t tmax,
                                                      const uint32_t* __restrict__ toff,
                                                      Tile* __restrict__ tiles) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
         uint32_t pos = cs[c];
         uint32_t left = cs[c + 1] - cs[c];
         while (left > 0) {
-            if (!open || fill == kTileMax || c - first + 1 > max_w) {
+            if (!open || fill == tmax || c - first + 1 > max_w) {
                 if (open) tiles[o++] = cur;
                 open = true;
                 fill = 0;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
                 cur.row = (uint32_t)r;
                 cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
             }
-            uint32_t take = kTileMax - fill < left ? kTileMax - fill : left;
+            uint32_t take = tmax - fill < left ? tmax - fill : left;
             fill += take;
             left -= take;
             pos += take;
@@ -369,7 +370,8 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     cute_status st = tmp.alloc(&cnt, (size_t)nrows + 1);
     if (st != CUTE_OK) return st;
     const unsigned nb = (unsigned)((nrows + 255) / 256);
-    hipLaunchKernelGGL(k_tiles_count, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows, max_w, cnt);
+    hipLaunchKernelGGL(k_tiles_count, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows, max_w,
+                       (uint32_t)g.tile_max, cnt);
     CUTE_HIP(hipGetLastError());
     if ((st = exclusive_scan(cnt, cnt, (size_t)nrows + 1, s)) != CUTE_OK) return st;
     uint32_t total = 0;
@@ -379,7 +381,7 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     if ((st = dalloc(&t, total, s)) != CUTE_OK) return st;
     if (total > 0) {
         hipLaunchKernelGGL(k_tiles_write, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows, max_w,
-                           cnt, t);
+                           (uint32_t)g.tile_max, cnt, t);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             dfree(t, s);

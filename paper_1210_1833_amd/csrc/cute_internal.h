@@ -146,6 +146,7 @@ struct GridHost {
     P64* p64;
     uint32_t* cstart;
     void* block;         // the one device allocation holding p64, p32 and cstart
+    int tile_max;        // most points in a home tile (1..64)
     double ms_build;
     GridView view() const;
 };

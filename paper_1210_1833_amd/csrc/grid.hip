@@ -368,6 +368,8 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
         return fail(CUTE_E_INVALID_ARG, "r_max must be >= 0");
     if (p->geom == CUTE_GEOM_BOX_PERIODIC && p->r_max >= 0.5 * p->box_size)
         return fail(CUTE_E_INVALID_ARG, "periodic r_max must be < L/2");
+    if (p->tile_points < 0 || p->tile_points > 64)
+        return fail(CUTE_E_INVALID_ARG, "tile_points must be in [0, 64]");
 
     int dev = 0;
     cute_status st = ensure_device_ready(&dev);
@@ -379,6 +381,7 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
     g.device = dev;
     g.geom = p->geom;
     g.n = n;
+    g.tile_max = p->tile_points > 0 ? p->tile_points : 64;
 
     EventTimer timer(s);
     TempList tmp(s);

@@ -41,7 +41,7 @@ def test_status_strings(lib):
 
 def test_build_grid_rejects_bad_arguments(lib):
     h = ctypes.c_void_p()
-    p = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0)
+    p = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0, 0)
     x = np.zeros(4)
     # NULL output
     assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
@@ -53,17 +53,17 @@ def test_build_grid_rejects_bad_arguments(lib):
     assert lib.cute_build_grid(None, None, None, 4, ctypes.byref(p), None,
                                ctypes.byref(h)) == cute.E_INVALID_ARG
     # periodic box without a size, and r_max >= L/2
-    pp = cute.GridParams(cute.GEOM_BOX_PERIODIC, 0.0, 0.0, 0.0, 0)
+    pp = cute.GridParams(cute.GEOM_BOX_PERIODIC, 0.0, 0.0, 0.0, 0, 0)
     assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pp),
                                None, ctypes.byref(h)) == cute.E_INVALID_ARG
-    pp = cute.GridParams(cute.GEOM_BOX_PERIODIC, 10.0, 5.0, 0.0, 0)
+    pp = cute.GridParams(cute.GEOM_BOX_PERIODIC, 10.0, 5.0, 0.0, 0, 0)
     assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pp),
                                None, ctypes.byref(h)) == cute.E_INVALID_ARG
     # unknown geometry and negative cell size
-    pg = cute.GridParams(7, 0.0, 0.0, 0.0, 0)
+    pg = cute.GridParams(7, 0.0, 0.0, 0.0, 0, 0)
     assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pg),
                                None, ctypes.byref(h)) == cute.E_INVALID_ARG
-    pc = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, -1.0, 0)
+    pc = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, -1.0, 0, 0)
     assert lib.cute_build_grid(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(pc),
                                None, ctypes.byref(h)) == cute.E_INVALID_ARG
     assert lib.cute_last_error()
@@ -128,22 +128,31 @@ def test_batch_rejects_bad_arguments(lib):
     lib.cute_batch_free(None)
 
 
-def test_tune_cell_size_rejects_bad_arguments(lib):
+def test_tune_grid_rejects_bad_arguments(lib):
     x = np.zeros(4)
-    p = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0)
+    p = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0, 0)
     b = cute.Binning(cute.BIN_MONO, [0.0, 1.0, 2.0]).c()
-    best = ctypes.c_double()
+    bc, bt = ctypes.c_double(), ctypes.c_int32()
     dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
     bad = np.array([-1.0])
-    # NULL best, NULL params, negative candidate, too many candidates
-    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
-                                   ctypes.byref(b), 1, 0, None, None, None, None) == cute.E_INVALID_ARG
-    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, None,
-                                   ctypes.byref(b), 1, 0, None, None, ctypes.byref(best),
-                                   None) == cute.E_INVALID_ARG
-    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
-                                   ctypes.byref(b), 1, 1, bad.ctypes.data_as(dp), None,
-                                   ctypes.byref(best), None) == cute.E_INVALID_ARG
-    assert lib.cute_tune_cell_size(x.ctypes.data, x.ctypes.data, x.ctypes.data, 4, ctypes.byref(p),
-                                   ctypes.byref(b), 1, 65, bad.ctypes.data_as(dp), None,
-                                   ctypes.byref(best), None) == cute.E_INVALID_ARG
+    badt = np.array([65], dtype=np.int32)
+    X = (x.ctypes.data, x.ctypes.data, x.ctypes.data, 4)
+    # NULL outputs, NULL params, negative side, tile size out of range, too many sides
+    assert lib.cute_tune_grid(*X, ctypes.byref(p), ctypes.byref(b), 1, 0, None, 0, None, None,
+                              None, None, None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_grid(*X, None, ctypes.byref(b), 1, 0, None, 0, None, None,
+                              ctypes.byref(bc), ctypes.byref(bt), None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_grid(*X, ctypes.byref(p), ctypes.byref(b), 1, 1, bad.ctypes.data_as(dp),
+                              0, None, None, ctypes.byref(bc), ctypes.byref(bt),
+                              None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_grid(*X, ctypes.byref(p), ctypes.byref(b), 1, 0, None, 1,
+                              badt.ctypes.data_as(ip), None, ctypes.byref(bc), ctypes.byref(bt),
+                              None) == cute.E_INVALID_ARG
+    assert lib.cute_tune_grid(*X, ctypes.byref(p), ctypes.byref(b), 1, 65, bad.ctypes.data_as(dp),
+                              0, None, None, ctypes.byref(bc), ctypes.byref(bt),
+                              None) == cute.E_INVALID_ARG
+    # a grid's tile size must be in [0, 64]
+    h = ctypes.c_void_p()
+    pt = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0, 65)
+    assert lib.cute_build_grid(*X, ctypes.byref(pt), None, ctypes.byref(h)) == cute.E_INVALID_ARG

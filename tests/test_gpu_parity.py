@@ -277,26 +277,28 @@ def test_multipoles_match_exact_rationals():
         assert np.all(np.abs(got[a] - ref[a]) <= 1e-12 * scale + 1e-300)
 
 
-def test_tuned_cell_size_counts_match_oracle():
-    """The cell-size tuner returns one of its candidates with a time for each;
-    counting with the chosen side gives the oracle's counts."""
+def test_tuned_grid_counts_match_oracle():
+    """The grid tuner returns one of its (cell, tile) candidates with a time for
+    each; counting with the chosen pair gives the oracle's counts."""
     d, _ = catalogs.config2(n_centres=150, per_blob=40, n_rand=10, box=300.0)
     re_, me = np.linspace(0, 40, 9), np.linspace(0, 1, 11)
     bn = cute.Binning(cute.BIN_RMU, re_, me)
-    best, times = cute.tune_cell_size(d, cute.GEOM_BOX_OPEN, bn)
-    say("tuned cell", best, times)
-    assert best in times and all(np.isfinite(v) and v > 0 for v in times.values())
-    got = gpu_counts(d, None, bn, cute.PREC_FP32_EDGE, cute.GEOM_BOX_OPEN, r_max=40.0, cell=best)
-    np.testing.assert_array_equal(got, oracle.count_pairs(d, None, obin(cute.BIN_RMU, re_, me)))
-    # explicit candidates in a periodic box (the grid keeps enough cells per
-    # side whatever the requested side, so every candidate is usable here)
+    cell, tile, times = cute.tune_grid(d, cute.GEOM_BOX_OPEN, bn)
+    say("tuned grid", cell, tile, times)
+    assert (cell, tile) in times and all(np.isfinite(v) and v > 0 for v in times.values())
+    g = cute.build_grid(d, cute.GEOM_BOX_OPEN, r_max=40.0, cell_size=cell, tile_points=tile)
+    np.testing.assert_array_equal(cute.count_pairs(g, None, bn, cute.PREC_FP32_EDGE),
+                                  oracle.count_pairs(d, None, obin(cute.BIN_RMU, re_, me)))
+    # explicit candidates in a periodic box, including small tiles
     u = catalogs.uniform_box(3000, 100.0, seed=5)
     e = np.linspace(0, 20, 11)
     mb = cute.Binning(cute.BIN_MONO, e)
-    best, times = cute.tune_cell_size(u, cute.GEOM_BOX_PERIODIC, mb, box_size=100.0, r_max=20.0,
-                                      candidates=[5.0, 10.0, 60.0])
-    assert best in (5.0, 10.0, 60.0) and set(times) == {5.0, 10.0, 60.0}
-    got = gpu_counts(u, None, mb, cute.PREC_FP32_EDGE, cute.GEOM_BOX_PERIODIC, L=100.0, r_max=20.0,
-                     cell=best)
-    np.testing.assert_array_equal(got, oracle.count_pairs(u, None, obin(cute.BIN_MONO, e,
-                                                                         periodic=True, L=100.0)))
+    cell, tile, times = cute.tune_grid(u, cute.GEOM_BOX_PERIODIC, mb, box_size=100.0, r_max=20.0,
+                                       cells=[5.0, 10.0], tiles=[1, 7, 64])
+    assert set(times) == {(c, t) for c in (5.0, 10.0) for t in (1, 7, 64)}
+    want = oracle.count_pairs(u, None, obin(cute.BIN_MONO, e, periodic=True, L=100.0))
+    for t in (1, 7, 64):
+        g = cute.build_grid(u, cute.GEOM_BOX_PERIODIC, box_size=100.0, r_max=20.0, cell_size=cell,
+                            tile_points=t)
+        for prec in EXACT:
+            np.testing.assert_array_equal(cute.count_pairs(g, None, mb, prec), want)

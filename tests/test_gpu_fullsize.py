@@ -1,4 +1,5 @@
-"""Parity at the full sizes of the light-cone (sigma-pi) and angular workloads.
+"""Parity at the full sizes of the light-cone (sigma-pi), angular and batched
+workloads.
 
 The oracle cannot count these catalogs whole, so the checks are
   * sampled outputs: the cross counts of 64 seeded home points against the
@@ -6,7 +7,7 @@ The oracle cannot count these catalogs whole, so the checks are
     the oracle computes one home point set at a time, bit-exact;
   * properties that hold at any size: the FP32_EDGE counts equal the FP64
     counts of the same full-size autocorrelation.
-Inputs are the full-size seeded catalogs of both workloads."""
+Inputs are the full-size seeded catalogs of the three workloads."""
 import sys
 
 import numpy as np
@@ -35,10 +36,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def dgrid(cat, geom, r_max):
+def dgrid(cat, geom, r_max, L=0.0):
     import torch
     xyz = [torch.from_numpy(np.ascontiguousarray(v)).to("cuda") for v in (cat.x, cat.y, cat.z)]
-    return cute.build_grid(xyz, geom, r_max=r_max)
+    return cute.build_grid(xyz, geom, box_size=L, r_max=r_max)
 
 
 def sample(cat, n, seed):
@@ -103,3 +104,48 @@ def test_theta_cap_full_size():
     np.testing.assert_array_equal(c32, c64)
     say("theta: %d pairs in range, %d evaluations, %.1f ms"
         % (st["pairs_in_range"], st["pair_evals"], st["ms_count"]))
+
+
+def test_batched_mocks_and_jackknife_full_size():
+    """The batched workload at full size: 256 periodic mocks (2e4 .. 5e5
+    points) with the monopole binning and jackknife catalogs of the 1e6-point
+    base with the r-mu binning, in one batch per precision. FP32_EDGE equals
+    FP64 item by item; sampled mocks equal their single counts; the smallest
+    mock equals the oracle; each jackknife catalog satisfies
+    DD(base) = DD(rest) + DD(region) + DR(rest, region)."""
+    import torch
+    L = 1000.0
+    say("generating the batched workload")
+    mocks, base, region = catalogs.config5()
+    mono = cute.Binning(cute.BIN_MONO, np.arange(31) * 5.0)
+    rmu = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(51) / 50.0, los=cute.LOS_Z)
+    gm = [dgrid(m, cute.GEOM_BOX_PERIODIC, 200.0, L) for m in mocks]
+    gb = dgrid(base, cute.GEOM_BOX_PERIODIC, 200.0, L)
+    gb2 = dgrid(base, cute.GEOM_BOX_PERIODIC, 200.0, L)
+    items = [cute.BatchItem(g, None, mono) for g in gm]
+    regs = [0, 57, 99]
+    for r in regs:
+        m = torch.from_numpy((region == r).astype(np.uint8)).cuda()
+        items += [cute.BatchItem(gb, None, rmu, mask_a=m),
+                  cute.BatchItem(gb, None, rmu, mask_a=1 - m),
+                  cute.BatchItem(gb, gb2, rmu, mask_a=m, mask_b=1 - m)]
+    res = {}
+    for prec in EXACT:
+        say("full-size batch, prec %d, %d items" % (prec, len(items)))
+        res[prec], st = cute.count_pairs_batched(items, prec, with_stats=True)
+        say("  %.1f ms, %d pair evaluations" % (st["ms_count"], st["pair_evals"]))
+    for k in range(len(items)):
+        np.testing.assert_array_equal(res[cute.PREC_FP32_EDGE][k], res[cute.PREC_FP64][k],
+                                      err_msg="item %d" % k)
+    got = res[cute.PREC_FP32_EDGE]
+    sizes = np.array([len(m) for m in mocks])
+    for k in list(np.argsort(sizes)[::32]) + [int(np.argmax(sizes))]:
+        np.testing.assert_array_equal(got[k], cute.count_pairs(gm[k], None, mono,
+                                                               cute.PREC_FP32_EDGE))
+    k0 = int(np.argmin(sizes))
+    ob = oracle.Binning(oracle.MONO, np.arange(31) * 5.0, periodic=True, L=L)
+    np.testing.assert_array_equal(got[k0], oracle.count_pairs(mocks[k0], None, ob, prune=True))
+    dd_base = cute.count_pairs(gb, None, rmu, cute.PREC_FP32_EDGE)
+    for q, r in enumerate(regs):
+        rest, reg, cross = got[len(gm) + 3 * q: len(gm) + 3 * q + 3]
+        np.testing.assert_array_equal(rest + reg + cross, dd_base, err_msg="region %d" % r)

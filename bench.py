@@ -153,6 +153,65 @@ def batched_leg(cute, torch, dev, runs=1):
                        "grids": round(t_grid, 2), "plan": round(t_plan, 2)}}
 
 
+# the paper's Table 2 (Server-GPU column: Tesla C2070, DR brute force, double
+# precision, seconds), quoted as context
+TABLE2_SERVER_GPU_S = {"xi_lin": 13.0, "xi_log": 20.0, "w_theta": 22.0, "xi_sigma_pi": 27.0}
+
+
+def table2_leg(cute, torch, dev, reps=3):
+    """The correlation functions of the paper's Table 2 on a synthetic
+    light-cone subset of its shape (RA, Dec in [0, 18] deg, z in [0.5, 0.6],
+    3e5 data and 3e5 randoms, uniform in volume): the DR histogram, brute
+    force (one cell holds every point) and with the cell list, FP32_EDGE and
+    FP64. Brute force and cell list must give the same counts."""
+    import catalogs
+    d, r = catalogs.table2()
+    du, ru = catalogs.unit_vectors(d), catalogs.unit_vectors(r)
+    funcs = {
+        "xi_lin": (cute.Binning(cute.BIN_MONO, np.linspace(0.0, 100.0, 257)), False),
+        "xi_log": (cute.Binning(cute.BIN_MONO, 100.0 * 10.0 ** ((np.arange(257) - 256) / 50.0)), False),
+        "w_theta": (cute.Binning(cute.BIN_THETA, np.deg2rad(np.linspace(0.0, 30.0, 257))), True),
+        "xi_sigma_pi": (cute.Binning(cute.BIN_SIGMAPI, np.linspace(0.0, 100.0, 65),
+                                     np.linspace(0.0, 100.0, 65), los=cute.LOS_MIDPOINT), False),
+    }
+
+    def dxyz(cat):
+        return [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (cat.x, cat.y, cat.z)]
+
+    out = {}
+    for name, (bn, sphere) in funcs.items():
+        geom = cute.GEOM_SPHERE if sphere else cute.GEOM_BOX_OPEN
+        reach = bn.edges1[-1] if sphere else float(np.hypot(bn.edges1[-1], bn.edges2[-1])
+                                                   if bn.edges2 is not None else bn.edges1[-1])
+        a, b = (dxyz(du), dxyz(ru)) if sphere else (dxyz(d), dxyz(r))
+        res = {}
+        for label, cell in (("brute", 1e9), ("cells", 0.0)):
+            ga = cute.build_grid(a, geom, r_max=reach, cell_size=cell)
+            gb = cute.build_grid(b, geom, r_max=reach, cell_size=cell)
+            for prec in ((cute.PREC_FP32_EDGE, cute.PREC_FP64) if label == "brute"
+                         else (cute.PREC_FP32_EDGE,)):
+                best, cnt, st = None, None, None
+                for _ in range(reps):
+                    cnt, st = cute.count_pairs(ga, gb, bn, prec, with_stats=True)
+                    best = st["ms_count"] if best is None else min(best, st["ms_count"])
+                res[(label, prec)] = (best, cnt, st)
+            ga.close()
+            gb.close()
+        c_ref = res[("brute", cute.PREC_FP64)][1]
+        exact = all(np.array_equal(v[1], c_ref) for v in res.values())
+        tb, _, sb = res[("brute", cute.PREC_FP32_EDGE)]
+        tc, _, sc = res[("cells", cute.PREC_FP32_EDGE)]
+        out[name] = {"bins": bn.nbins, "dr_pairs": len(d) * len(r),
+                     "brute_fp32_edge_s": round(tb / 1e3, 5),
+                     "brute_fp64_s": round(res[("brute", cute.PREC_FP64)][0] / 1e3, 5),
+                     "cell_list_fp32_edge_s": round(tc / 1e3, 5),
+                     "brute_gpair_per_s": round(sb["pair_evals"] / (tb * 1e-3) / 1e9, 1),
+                     "cell_list_pair_evals": int(sc["pair_evals"]),
+                     "pairs_in_range": int(sb["pairs_in_range"]), "bit_exact": exact,
+                     "paper_server_gpu_s": TABLE2_SERVER_GPU_S[name]}
+    return out
+
+
 def committed_traffic():
     """HBM bytes per count launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; None otherwise."""
@@ -181,6 +240,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched mock/jackknife workload")
     ap.add_argument("--no-tune", action="store_true", help="skip the cell-size tuner leg")
+    ap.add_argument("--no-table2", action="store_true",
+                    help="skip the correlation functions of the paper's Table 2")
     ap.add_argument("--cell-size", type=float, default=0.0,
                     help="cell side of the grid (0 = the library's choice)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -305,6 +366,9 @@ def main():
         out["tuned_cell"] = tuned_leg(cute, xyz, bn, counts, c32)
     if not args.no_batched:
         out["batched"] = batched_leg(cute, torch, dev)
+    if not args.no_table2:
+        log("bench: the paper's Table 2 functions")
+        out["paper_table2"] = table2_leg(cute, torch, dev)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(d)

@@ -141,6 +141,36 @@ def sky_cap_lightcone(n: int, seed: int, ra_max_deg: float = 60.0,
     return _shuffled(g, xyz)
 
 
+def lightcone_box(n: int, seed: int, ra_max_deg: float = 18.0, dec_max_deg: float = 18.0,
+                  z_lo: float = 0.5, z_hi: float = 0.6) -> Catalog:
+    """Points uniform in comoving volume within RA in [0, ra_max], Dec in
+    [0, dec_max] and redshift in [z_lo, z_hi] (flat LCDM, Om=0.3), observer
+    at the origin: the shape of the light-cone subset the paper times its
+    Table 2 on."""
+    g = rng(seed)
+    ra = np.deg2rad(g.random(n) * ra_max_deg)
+    sin_dec = g.random(n) * np.sin(np.deg2rad(dec_max_deg))
+    zs, chi_tab = comoving_distance_table()
+    c0, c1 = np.interp([z_lo, z_hi], zs, chi_tab)
+    chi = np.cbrt(c0 ** 3 + g.random(n) * (c1 ** 3 - c0 ** 3))
+    cos_dec = np.sqrt(1.0 - sin_dec * sin_dec)
+    xyz = np.stack([chi * cos_dec * np.cos(ra), chi * cos_dec * np.sin(ra),
+                    chi * sin_dec], axis=1)
+    return _shuffled(g, xyz)
+
+
+def table2(n: int = 300_000):
+    """Data and random catalogs of the Table 2 shape (about 3e5 points each).
+    Returns (data, randoms) as 3-D positions; normalise them for angles."""
+    return lightcone_box(n, seed=6001), lightcone_box(n, seed=6002)
+
+
+def unit_vectors(cat: Catalog) -> Catalog:
+    """The directions of a catalog's positions (observer at the origin)."""
+    xyz = cat.stacked()
+    return Catalog.from_xyz(xyz / np.linalg.norm(xyz, axis=1, keepdims=True))
+
+
 # ----------------------------------------------------------------------------
 # Unit vectors in a spherical cap (angular workload)
 # ----------------------------------------------------------------------------

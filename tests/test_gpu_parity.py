@@ -302,3 +302,21 @@ def test_tuned_grid_counts_match_oracle():
                             tile_points=t)
         for prec in EXACT:
             np.testing.assert_array_equal(cute.count_pairs(g, None, mb, prec), want)
+
+
+@pytest.mark.parametrize("cell", [0.0, 1e9])
+def test_table2_binnings(cell):
+    """The binnings of the paper's Table 2 (256 linear r bins to 100, 256 log
+    bins at 50 per decade, 64 x 64 sigma-pi, 256 linear theta bins to 30 deg)
+    on DR of a small light-cone subset of its shape, with the cell list and
+    with one cell holding every point (brute force)."""
+    d, r = catalogs.lightcone_box(1500, seed=11), catalogs.lightcone_box(1500, seed=12)
+    lin = np.linspace(0.0, 100.0, 257)
+    check_case("t2-lin-%g" % cell, d, r, cute.BIN_MONO, lin, cell=cell)
+    check_case("t2-log-%g" % cell, d, r, cute.BIN_MONO, 100.0 * 10.0 ** ((np.arange(257) - 256) / 50.0),
+               cell=cell)
+    sp = np.linspace(0.0, 100.0, 65)
+    check_case("t2-sp-%g" % cell, d, r, cute.BIN_SIGMAPI, sp, sp, los=cute.LOS_MIDPOINT, cell=cell)
+    du, ru = catalogs.unit_vectors(d), catalogs.unit_vectors(r)
+    check_case("t2-theta-%g" % cell, du, ru, cute.BIN_THETA, np.deg2rad(np.linspace(0.0, 30.0, 257)),
+               geom=cute.GEOM_SPHERE, cell=(1e9 if cell else 0.0))

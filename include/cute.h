@@ -260,6 +260,28 @@ cute_status cute_count_pairs_batched(const cute_batch_item* items, int32_t n_ite
                                      int32_t counts_on_device, cute_count_stats* st,
                                      void* stream);
 
+/* ---- Jackknife by region decomposition ---------------------------------------
+ * Jackknife error bars need the autocorrelation of the catalog with one
+ * region left out, for each of K regions (the pair counts of Sec. 2.2 on K
+ * sub-catalogs). Here all of them come from two passes over the grid,
+ * whatever K: the total, and
+ * one full-stencil pass that finds for each region k the pairs with at least
+ * one point in it (T_k); then jack_k = total - T_k. The counts equal those of
+ * cute_count_pairs on each catalog without region k (bit-exact for FP64 and
+ * FP32_EDGE).
+ * g: a 3-D grid (BOX_OPEN or BOX_PERIODIC). region: g's n labels in its input
+ * order, each in [0, K) (device pointer if regions_on_device). K: 1..65535.
+ * total: n1 * max(n2, 1) uint64 (host), the autocorrelation of g.
+ * jack: K * n1 * max(n2, 1) uint64 (host), row k = catalog without region k.
+ * st (nullable): both passes together.
+ * Errors: CUTE_E_INVALID_ARG for NULL pointers, K out of range or a label
+ * outside [0, K); CUTE_E_UNSUPPORTED for a SPHERE grid or a stencil too large
+ * to tabulate; the errors of cute_count_pairs. */
+cute_status cute_count_jackknife(const cute_grid* g, const int32_t* region, int32_t regions_on_device,
+                                 int32_t K, const cute_binning* bins, cute_precision prec,
+                                 uint64_t* total, uint64_t* jack, cute_count_stats* st,
+                                 void* stream);
+
 /* Estimator of Sec. 2.2 per bin (xi has the shape of the counts).
  * NATURAL: dd, rr; LS: dd, dr, rr; BOX: dd only (MONO binning, periodic
  * volume box_size^3, expected count N(N-1)/2 * V_shell / L^3 with the exact

@@ -28,7 +28,7 @@ BATCH_GRAPH, BATCH_EAGER = range(2)
 
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
             "cute_tune_grid", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
-            "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched",
+            "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched", "cute_count_jackknife",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
 
@@ -121,6 +121,10 @@ def load():
     lib.cute_count_pairs_batched.argtypes = [ctypes.POINTER(CBatchItem), ctypes.c_int32,
                                              ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int32,
                                              ctypes.POINTER(CountStats), vp]
+    lib.cute_count_jackknife.restype = ctypes.c_int
+    lib.cute_count_jackknife.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(CBinning), ctypes.c_int, vp, vp,
+                                         ctypes.POINTER(CountStats), vp]
     lib.cute_xi_estimate.restype = ctypes.c_int
     lib.cute_xi_estimate.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(CBinning), ctypes.c_double, dp]
@@ -457,6 +461,38 @@ def count_pairs_batched(items, prec: int = PREC_FP32_EDGE, stream=None, with_sta
                                         _stream_handle(stream)))
     res = [o.reshape(it.binning.shape) for o, it in zip(outs, items)]
     return (res, st.as_dict()) if with_stats else res
+
+
+def count_jackknife(grid: Grid, region, n_regions: int, binning: Binning,
+                    prec: int = PREC_FP32_EDGE, stream=None, with_stats: bool = False):
+    """cute_count_jackknife: (total, jack) with jack[k] the autocorrelation of
+    the grid's catalog without the points of region k. ``region``: one label
+    in [0, n_regions) per point, in the grid's input order (numpy int32 on
+    the host or a torch int32 tensor on the device)."""
+    lib = load()
+    try:
+        import torch
+        is_t = isinstance(region, torch.Tensor)
+    except ImportError:  # pragma: no cover
+        is_t = False
+    if is_t:
+        reg = region.contiguous()
+        if reg.dtype != torch.int32 or reg.numel() != grid.n:
+            raise ValueError("region must be int32 with one label per point")
+        ptr, on_dev = reg.data_ptr(), int(reg.is_cuda)
+    else:
+        reg = np.ascontiguousarray(region, dtype=np.int32)
+        if reg.size != grid.n:
+            raise ValueError("region must have one label per point")
+        ptr, on_dev = reg.ctypes.data, 0
+    total = np.zeros(binning.nbins, dtype=np.uint64)
+    jack = np.zeros((int(n_regions), binning.nbins), dtype=np.uint64)
+    st = CountStats()
+    _check(lib.cute_count_jackknife(grid.handle, ptr, on_dev, int(n_regions), ctypes.byref(binning.c()),
+                                    int(prec), total.ctypes.data, jack.ctypes.data, ctypes.byref(st),
+                                    _stream_handle(stream)))
+    res = (total.reshape(binning.shape), jack.reshape((int(n_regions),) + binning.shape))
+    return (res + (st.as_dict(),)) if with_stats else res
 
 
 def xi_estimate(estimator: int, dd, dr, rr, nd: int, nr: int, binning: Binning,

@@ -406,15 +406,22 @@ struct WaveState {
 // lanes hitting the same bin use different banks. copies is a power of two:
 // word = (bin << log2(copies)) | (lane & (copies - 1)).
 __device__ __forceinline__ void hist_add(unsigned long long* hist, uint32_t bin, int copies,
-                                         int lane) {
+                                         int lane, uint32_t w = 1u) {
     const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
-    atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], 1ull);
+    atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], (unsigned long long)w);
 }
 
 // One increment at an LDS byte address (the lane's copy already folded in).
-__device__ __forceinline__ void lds_add(uint32_t byte_addr) {
+__device__ __forceinline__ void lds_add(uint32_t byte_addr, uint32_t w) {
     __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned long long*)(uintptr_t)byte_addr,
-                           1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                           (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Weight of a pair in a region pass: 1 if the neighbour lies in the home
+// region, 2 otherwise (1 outside region passes).
+__device__ __forceinline__ uint32_t pair_weight(const CountArgs& P, uint32_t j) {
+    if (P.regs == nullptr) return 1u;
+    return P.regs[j] == (uint16_t)P.region ? 1u : 2u;
 }
 
 // Re-test up to 64 queued pairs per pass, one per lane, through the canonical
@@ -436,7 +443,7 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
             const P64 p = P.A.p64[i];
             const P64 q = P.B.p64[j];
             k = classify_pair64<MODE, EST>(P, T1, T2, p, q);
-            if (k != kNoBin) hist_add(hist, k, P.copies, lane);
+            if (k != kNoBin) hist_add(hist, k, P.copies, lane, pair_weight(P, j));
             // the FP32-only decision of the same pair, as the main loop made it
             const float4 a = P.A.p32[i];
             const float4 b = P.B.p32[j];
@@ -519,7 +526,8 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
                                        const float2* B1, const float2* B2, const double* T1,
                                        const double* T2, int lane, bool lvalid, bool lmask,
                                        uint32_t lj, uint32_t lcode, float qx, float qy, float qz,
-                                       float qlx, float qly, float qlz, uint32_t lb, uint32_t h) {
+                                       float qlx, float qly, float qlz, uint32_t lb, uint32_t lw,
+                                       uint32_t h) {
     float hx[U], hy[U], hz[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -534,7 +542,8 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     bool cnt[U], amb[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
-        const bool act = lvalid & hv[u] & (!MASKED | !lmask | (lj > h + u));
+        const bool act = lvalid & hv[u] &
+                         (!MASKED | !lmask | (lj > h + u) | ((P.selfx != 0) & (lj < h + u)));
         const float dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
         float lx = 0.f, ly = 0.f, lz = 0.f;
         if (MODE == M_RMU_MID || MODE == M_SIGMAPI) {
@@ -569,7 +578,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) lds_add(off[u]);
+        if (cnt[u]) lds_add(off[u], lw);
     if (PREC == P_FP32E && any_amb) {
         uint64_t m[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -583,7 +592,7 @@ template <int MODE, int EST, bool PM, bool MASKED, bool SHIFTED, uint32_t U>
 __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const double* T1,
                                        const double* T2, int lane, bool lvalid, bool lmask,
                                        uint32_t lj, double qx, double qy, double qz, double sx, double sy,
-                                       double sz, uint32_t h) {
+                                       double sz, uint32_t lw, uint32_t h) {
     double hx[U], hy[U], hz[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -598,7 +607,8 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     bool cnt[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
-        const bool act = lvalid & hv[u] & (!MASKED | !lmask | (lj > h + u));
+        const bool act = lvalid & hv[u] &
+                         (!MASKED | !lmask | (lj > h + u) | ((P.selfx != 0) & (lj < h + u)));
         double dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
         if (SHIFTED) {
             // the neighbour's periodic image: equal to the minimum-image wrap
@@ -638,7 +648,7 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane);
+        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane, lw);
 }
 
 // The chunk being assembled from neighbour spans (per-lane fields in VGPRs,
@@ -660,6 +670,7 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     bool lvalid = (uint32_t)lane < C.filled;
     // a neighbour excluded by the point mask leaves its lane idle
     if (PM && P.mbB != nullptr && lvalid) lvalid = ((P.mbB[C.lj >> 5] >> (C.lj & 31u)) & 1u) == 0u;
+    const uint32_t lw = lvalid ? pair_weight(P, C.lj) : 1u;
     if (PREC == P_FP64) {
         double qx = 0.0, qy = 0.0, qz = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
         if (lvalid) {
@@ -676,10 +687,10 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         uint32_t h = ts;                                                                        \
         for (; h + U <= te; h += U)                                                             \
             step64<MODE, EST, PM, MSK, SH, U>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
-                                          sx, sy, sz, h);                                       \
+                                          sx, sy, sz, lw, h);                                   \
         for (; h < te; h++)                                                                     \
             step64<MODE, EST, PM, MSK, SH, 1>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
-                                          sx, sy, sz, h);                                       \
+                                          sx, sy, sz, lw, h);                                   \
     }
         if (C.masked) {
             if (C.shifted) CUTE_RUN64(true, true) else CUTE_RUN64(true, false)
@@ -711,11 +722,11 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         for (; h + U <= te; h += U)                                                                \
             step32<MODE, PREC, EST, PM, MSK, LOW, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
                                                      C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
-                                                     qlz, lb, h);                                  \
+                                                     qlz, lb, lw, h);                                  \
         for (; h < te; h++)                                                                        \
             step32<MODE, PREC, EST, PM, MSK, LOW, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
                                                      C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
-                                                     qlz, lb, h);                                  \
+                                                     qlz, lb, lw, h);                                  \
     }
         // bins starting at zero separation have no low-side clean "out"
         const bool low = !(P.out_lo < 0.0f) || MODE == M_SIGMAPI;
@@ -737,7 +748,10 @@ template <int MODE, int PREC, int EST, bool PM>
 __device__ void feed(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
                      const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
                      uint32_t te, uint32_t a0, uint32_t a1, uint32_t code, bool masked) {
-    if (masked && a1 > a0) {
+    if (masked && a1 > a0 && P.selfx) {
+        // the tile against itself: every pair but the point with itself
+        W.evals += (uint64_t)(te - ts) * (a1 - a0) - (a1 - a0);
+    } else if (masked && a1 > a0) {
         // lanes with neighbour j pair with the home points h < j: sum of (j - ts)
         const uint64_t lo_ = a0 - ts, hi_ = a1 - 1u - ts;
         W.evals += (lo_ + hi_) * (hi_ - lo_ + 1u) / 2u;
@@ -892,6 +906,7 @@ __device__ bool gen_spans(const CountArgs& P, const Tile& tl, int lane, SpanBuf&
             const int left = (int)uni(st[4 * e + 2]), right = (int)uni(st[4 * e + 3]);
             const int byu = cy + ody, bzu = cz + odz;
             const bool same = P.is_auto && ody == 0 && odz == 0;
+            const bool home = P.selfx && ody == 0 && odz == 0;
             int x0 = same ? c0 : c0 - left, x1 = c1 + right;
             int ry = byu, rz = bzu, ky = 0, kz = 0;
             if (P.periodic) {
@@ -915,8 +930,21 @@ __device__ bool gen_spans(const CountArgs& P, const Tile& tl, int lane, SpanBuf&
                 const int a1 = x1 < lim ? x1 : lim;
                 const uint32_t code =
                     (uint32_t)(kx + 1) | ((uint32_t)(ky + 1) << 2) | ((uint32_t)(kz + 1) << 4);
-                push_cells(S, lane, cs, rb, a0 - kx * B.nx, a1 - kx * B.nx, code,
-                           same && kx == 0 && a0 == c0, ts, te);
+                if (home && kx == 0 && a0 <= c0 && c1 <= a1) {
+                    // full stencil over one catalog: the tile's own cells are
+                    // split around the tile, whose points pair with all but
+                    // themselves (the j != i test)
+                    if (a0 < c0) push_cells(S, lane, cs, rb, a0, c0 - 1, code, false, ts, te);
+                    const uint32_t j0 = uni(cs[rb + (uint32_t)c0]);
+                    const uint32_t j1 = uni(cs[rb + (uint32_t)c1 + 1u]);
+                    push_span(S, lane, j0, ts, code, false);
+                    push_span(S, lane, ts, te, code, true);
+                    push_span(S, lane, te, j1, code, false);
+                    if (c1 < a1) push_cells(S, lane, cs, rb, c1 + 1, a1, code, false, ts, te);
+                } else {
+                    push_cells(S, lane, cs, rb, a0 - kx * B.nx, a1 - kx * B.nx, code,
+                               same && kx == 0 && a0 == c0, ts, te);
+                }
                 a0 = a1 + 1;
             }
         }

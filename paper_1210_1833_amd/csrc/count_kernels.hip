@@ -171,68 +171,79 @@ cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int
 
 // Home tiles: each row of cells is cut into runs of at most tmax points
 // whose x-extent stays within max_w cells (so that periodic stencils never
-// wrap onto themselves); a cell with more points is split. One thread walks
-// one row.
-__global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict__ cstart, int nx,
+// wrap onto themselves); a cell with more points is split. With a region per
+// point (points sorted by region inside each cell), a tile also ends where
+// the region changes. One thread walks one row; with out == nullptr it only
+// counts the tiles.
+__device__ uint32_t walk_row_tiles(const uint32_t* __restrict__ cstart, const uint16_t* __restrict__ reg,
+                                   int nx, int r, int max_w, uint32_t tmax, Tile* __restrict__ out) {
+    const uint32_t* cs = cstart + (size_t)r * nx;
+    uint32_t o = 0, fill = 0;
+    int first = -1;
+    uint16_t cur_rg = 0;
+    Tile cur{0u, 0u, 0u, 0u};
+    bool open = false;
+    for (int c = 0; c < nx; c++) {
+        uint32_t pos = cs[c];
+        const uint32_t end = cs[c + 1];
+        while (pos < end) {
+            // the next run of points of one region inside this cell
+            uint32_t run = end - pos;
+            uint16_t rg = 0;
+            if (reg != nullptr) {
+                rg = reg[pos];
+                run = 1;
+                while (pos + run < end && reg[pos + run] == rg) run++;
+            }
+            while (run > 0) {
+                if (!open || fill == tmax || c - first + 1 > max_w || rg != cur_rg) {
+                    if (open) {
+                        if (out) out[o] = cur;
+                        o++;
+                    }
+                    open = true;
+                    fill = 0;
+                    first = c;
+                    cur_rg = rg;
+                    cur.start = pos;
+                    cur.end = pos;
+                    cur.row = (uint32_t)r;
+                    cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
+                }
+                const uint32_t take = tmax - fill < run ? tmax - fill : run;
+                fill += take;
+                run -= take;
+                pos += take;
+                cur.end = pos;
+                cur.c0c1 = (cur.c0c1 & 0xffffu) | ((uint32_t)c << 16);
+            }
+        }
+    }
+    if (open) {
+        if (out) out[o] = cur;
+        o++;
+    }
+    return o;
+}
+
+__global__ __launch_bounds__(256) void k_tiles_count(const uint32_t* __restrict__ cstart,
+                                                     const uint16_t* __restrict__ reg, int nx,
                                                      int nrows, int max_w, uint32_t tmax,
                                                      uint32_t* __restrict__ ntile) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r == 0) ntile[nrows] = 0u;  // the scan's last entry becomes the total
     if (r >= nrows) return;
-    const uint32_t* cs = cstart + (size_t)r * nx;
-    uint32_t cnt = 0, fill = 0;
-    int first = -1;
-    for (int c = 0; c < nx; c++) {
-        uint32_t left = cs[c + 1] - cs[c];
-        while (left > 0) {
-            if (fill == 0 || fill == tmax || c - first + 1 > max_w) {
-                cnt++;
-                fill = 0;
-                first = c;
-            }
-            uint32_t take = tmax - fill < left ? tmax - fill : left;
-            fill += take;
-            left -= take;
-        }
-    }
-    ntile[r] = cnt;
+    ntile[r] = walk_row_tiles(cstart, reg, nx, r, max_w, tmax, nullptr);
 }
 
-__global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict__ cstart, int nx,
+__global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict__ cstart,
+                                                     const uint16_t* __restrict__ reg, int nx,
                                                      int nrows, int max_w, uint32_t tmax,
                                                      const uint32_t* __restrict__ toff,
                                                      Tile* __restrict__ tiles) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
-    const uint32_t* cs = cstart + (size_t)r * nx;
-    uint32_t o = toff[r];
-    uint32_t fill = 0;
-    int first = -1;
-    Tile cur;
-    bool open = false;
-    for (int c = 0; c < nx; c++) {
-        uint32_t pos = cs[c];
-        uint32_t left = cs[c + 1] - cs[c];
-        while (left > 0) {
-            if (!open || fill == tmax || c - first + 1 > max_w) {
-                if (open) tiles[o++] = cur;
-                open = true;
-                fill = 0;
-                first = c;
-                cur.start = pos;
-                cur.end = pos;
-                cur.row = (uint32_t)r;
-                cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
-            }
-            uint32_t take = tmax - fill < left ? tmax - fill : left;
-            fill += take;
-            left -= take;
-            pos += take;
-            cur.end = pos;
-            cur.c0c1 = (cur.c0c1 & 0xffffu) | ((uint32_t)c << 16);
-        }
-    }
-    if (open) tiles[o++] = cur;
+    (void)walk_row_tiles(cstart, reg, nx, r, max_w, tmax, tiles + toff[r]);
 }
 
 namespace {
@@ -361,7 +372,7 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
 }
 
 cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
-                        uint32_t* ntiles) {
+                        uint32_t* ntiles, const uint16_t* reg) {
     *tiles = nullptr;
     *ntiles = 0;
     const int nrows = g.ny * g.nz;
@@ -370,7 +381,7 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     cute_status st = tmp.alloc(&cnt, (size_t)nrows + 1);
     if (st != CUTE_OK) return st;
     const unsigned nb = (unsigned)((nrows + 255) / 256);
-    hipLaunchKernelGGL(k_tiles_count, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows, max_w,
+    hipLaunchKernelGGL(k_tiles_count, dim3(nb), dim3(256), 0, s, g.cstart, reg, g.nx, nrows, max_w,
                        (uint32_t)g.tile_max, cnt);
     CUTE_HIP(hipGetLastError());
     if ((st = exclusive_scan(cnt, cnt, (size_t)nrows + 1, s)) != CUTE_OK) return st;
@@ -380,8 +391,8 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     Tile* t = nullptr;
     if ((st = dalloc(&t, total, s)) != CUTE_OK) return st;
     if (total > 0) {
-        hipLaunchKernelGGL(k_tiles_write, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows, max_w,
-                           (uint32_t)g.tile_max, cnt, t);
+        hipLaunchKernelGGL(k_tiles_write, dim3(nb), dim3(256), 0, s, g.cstart, reg, g.nx, nrows,
+                           max_w, (uint32_t)g.tile_max, cnt, t);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             dfree(t, s);

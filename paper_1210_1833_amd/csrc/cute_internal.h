@@ -110,6 +110,12 @@ struct CountArgs {
     // precomputed neighbour rows (see ItemGeom::stencil), or nullptr
     const int4* stencil;
     int nst;
+    // region pass of the jackknife (full stencil over one catalog): sorted-
+    // order region of each point, the home region of this item's tiles, and
+    // the j != i test in the home tile's own span; regs == nullptr otherwise
+    const uint16_t* regs;
+    int region;
+    int selfx;
     // point masks (batched counts): bit i of word i / 32 set = sorted point i
     // excluded; nullptr = no mask
     const uint32_t* mbA;
@@ -204,8 +210,9 @@ cute_status exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, hipStrea
 
 // home tiles of grid g (runs of <= 64 points in one row, x-extent <= max_w
 // cells); *tiles is a stream-ordered allocation owned by the caller
+// (reg: optional sorted-order region per point; tiles then never mix regions)
 cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
-                        uint32_t* ntiles);
+                        uint32_t* ntiles, const uint16_t* reg = nullptr);
 
 // reorder *tiles longest first by estimated cost (needs the precomputed
 // neighbour rows on the device; a no-op without them)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "cute_internal.h"
 
@@ -37,17 +38,16 @@ inline void dfree(void* p, hipStream_t s) {
 // RAII list of stream-ordered temporaries.
 struct TempList {
     hipStream_t s;
-    void* ptrs[16];
-    int n = 0;
+    std::vector<void*> ptrs;
     explicit TempList(hipStream_t st) : s(st) {}
     template <typename T>
     cute_status alloc(T** p, size_t count) {
         cute_status st = dalloc(p, count, s);
-        if (st == CUTE_OK) ptrs[n++] = *p;
+        if (st == CUTE_OK) ptrs.push_back(*p);
         return st;
     }
     ~TempList() {
-        for (int i = 0; i < n; i++) dfree(ptrs[i], s);
+        for (void* p : ptrs) dfree(p, s);
     }
 };
 

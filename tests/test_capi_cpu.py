@@ -156,3 +156,17 @@ def test_tune_grid_rejects_bad_arguments(lib):
     h = ctypes.c_void_p()
     pt = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.0, 0.0, 0, 65)
     assert lib.cute_build_grid(*X, ctypes.byref(pt), None, ctypes.byref(h)) == cute.E_INVALID_ARG
+
+
+def test_jackknife_rejects_bad_arguments(lib):
+    b = cute.Binning(cute.BIN_MONO, [0.0, 1.0, 2.0]).c()
+    reg = np.zeros(4, dtype=np.int32)
+    out = np.zeros(8, dtype=np.uint64)
+    # NULL grid, then a K out of range (checked before the grid is used)
+    assert lib.cute_count_jackknife(None, reg.ctypes.data, 0, 1, ctypes.byref(b), 1,
+                                    out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG
+    fake = ctypes.c_void_p(1)
+    assert lib.cute_count_jackknife(fake, reg.ctypes.data, 0, 0, ctypes.byref(b), 1,
+                                    out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG
+    assert lib.cute_count_jackknife(fake, None, 0, 4, ctypes.byref(b), 1,
+                                    out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG

@@ -473,22 +473,27 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
     return tail;
 }
 
-// Queue the lanes set in m[u] (pair: home h + u, this lane's neighbour).
-template <int MODE, int EST, uint32_t U>
-__device__ __attribute__((noinline)) uint32_t enqueue(
+// Queue the ambiguous pairs of a chunk: for every home offset o set in hsum,
+// the lanes whose bit o is set in ambh (pair: home ts + o, the lane's
+// neighbour). Drains whenever 64 or more pairs are waiting.
+template <int MODE, int EST>
+__device__ __attribute__((noinline)) uint32_t enqueue_chunk(
     const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
     unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
-    const double* T2, int lane, uint32_t tail, uint32_t h, uint32_t lj, uint32_t lcode,
-    uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3) {
+    const double* T2, int lane, uint32_t tail, uint32_t ts, uint32_t lj, uint32_t lcode,
+    uint64_t ambh, uint64_t hsum) {
     tail = uni(tail);
-    for (uint32_t u = 0; u < U; u++) {
-        const uint64_t m = u == 0 ? m0 : (u == 1 ? m1 : (u == 2 ? m2 : m3));
-        if (m == 0) continue;
+    uint32_t hlo = uni((uint32_t)hsum), hhi = uni((uint32_t)(hsum >> 32));
+    while (hlo | hhi) {
+        const uint32_t o = hlo ? (uint32_t)__builtin_ctz(hlo) : 32u + (uint32_t)__builtin_ctz(hhi);
+        if (o < 32u) hlo &= hlo - 1u; else hhi &= hhi - 1u;
+        const bool mine = ((ambh >> o) & 1ull) != 0ull;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(mine);
         const uint32_t pre =
             __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if ((m >> lane) & 1ull) {
+        if (mine) {
             const uint32_t pos = tail + pre;
-            qi[pos] = h + u;
+            qi[pos] = ts + o;
             qj[pos] = lj;
             qc[pos] = lcode;
         }
@@ -527,7 +532,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
                                        const double* T2, int lane, bool lvalid, bool lmask,
                                        uint32_t lj, uint32_t lcode, float qx, float qy, float qz,
                                        float qlx, float qly, float qlz, uint32_t lb, uint32_t lw,
-                                       uint32_t h) {
+                                       uint32_t ts, uint64_t& ambh, uint64_t& hsum, uint32_t h) {
     float hx[U], hy[U], hz[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -580,11 +585,14 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     for (uint32_t u = 0; u < U; u++)
         if (cnt[u]) lds_add(off[u], lw);
     if (PREC == P_FP32E && any_amb) {
-        uint64_t m[4] = {0, 0, 0, 0};
+        // remember the pair for the end of the chunk: bit (home - ts) of this
+        // lane's mask, and the home offset in the wave's mask
 #pragma unroll
-        for (uint32_t u = 0; u < U; u++) m[u] = __builtin_amdgcn_ballot_w64(amb[u]);
-        W.tail = enqueue<MODE, EST, U>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,
-                                       W.tail, h, lj, lcode, m[0], m[1], m[2], m[3]);
+        for (uint32_t u = 0; u < U; u++) {
+            const uint64_t bit = 1ull << (h + u - ts);
+            if (__builtin_amdgcn_ballot_w64(amb[u])) hsum |= bit;
+            if (amb[u]) ambh |= bit;
+        }
     }
 }
 
@@ -722,12 +730,15 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         for (; h + U <= te; h += U)                                                                \
             step32<MODE, PREC, EST, PM, MSK, LOW, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
                                                      C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
-                                                     qlz, lb, lw, h);                                  \
+                                                     qlz, lb, lw, ts, ambh, hsum, h);              \
         for (; h < te; h++)                                                                        \
             step32<MODE, PREC, EST, PM, MSK, LOW, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
                                                      C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
-                                                     qlz, lb, lw, h);                                  \
+                                                     qlz, lb, lw, ts, ambh, hsum, h);              \
     }
+        // ambiguous pairs of this chunk: per lane, bit (home - ts); per wave,
+        // the home offsets with any (queued once the home loop is done)
+        uint64_t ambh = 0, hsum = 0;
         // bins starting at zero separation have no low-side clean "out"
         const bool low = !(P.out_lo < 0.0f) || MODE == M_SIGMAPI;
         if (C.masked) {
@@ -735,6 +746,9 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         } else {
             if (low) CUTE_RUN32(false, true) else CUTE_RUN32(false, false)
         }
+        if (PREC == P_FP32E && hsum != 0ull)
+            W.tail = enqueue_chunk<MODE, EST>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1,
+                                              T2, lane, W.tail, ts, C.lj, C.lcode, ambh, hsum);
 #undef CUTE_RUN32
     }
     C.filled = 0;

@@ -14,7 +14,6 @@ namespace {
 
 constexpr uint32_t kNoBin = 0xffffffffu;
 constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr uint32_t kTileMax = 64;      // home points per tile
 
 // Read-only device memory seen through the constant address space: loads at
 // wave-uniform addresses become scalar (s_load) loads into SGPRs.

@@ -7,6 +7,9 @@ GPU library.
 
 * ``count_pairs``: plain FP64 pair counting (``oracle.c``), the definition of
   the pair count in Sec. 2.2 of the paper evaluated pair by pair.
+* ``pixel_map`` and ``count_weighted``: the pixelised angular correlation
+  (Sec. 3.4): objects binned into equal-area (cos theta, phi) pixels, and pair
+  counts in which each pixel carries its occupancy as a weight.
 * ``estimators``: the natural, Landy-Szalay and periodic-box estimators of
   Sec. 2.2 and the Legendre multipoles of Sec. 2.1, in exact rational
   arithmetic.
@@ -75,6 +78,17 @@ def _load():
             lib.oracle_rmax.argtypes = [ctypes.POINTER(_Binning)]
             lib.oracle_nbins.restype = ctypes.c_int
             lib.oracle_nbins.argtypes = [ctypes.POINTER(_Binning)]
+            lib.oracle_pixel_ids.restype = ctypes.c_int
+            lib.oracle_pixel_ids.argtypes = [ctypes.c_void_p] * 3 + [
+                ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+            lib.oracle_pixel_centres.restype = ctypes.c_int
+            lib.oracle_pixel_centres.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                                 ctypes.c_int] + [ctypes.c_void_p] * 3
+            lib.oracle_count_weighted.restype = ctypes.c_int
+            lib.oracle_count_weighted.argtypes = (
+                [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
+                + [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Binning), ctypes.c_int,
+                   ctypes.c_void_p])
             _lib = lib
     return _lib
 
@@ -162,3 +176,73 @@ def rmax(binning: Binning) -> float:
     lib = _load()
     cb = binning._c()
     return float(lib.oracle_rmax(ctypes.byref(cb)))
+
+
+def pixel_ids(cat, n_cth: int, n_phi: int):
+    """Pixel id (ring * n_phi + sector) of every unit vector of ``cat``."""
+    lib = _load()
+    x, y, z = _xyz(cat)
+    ids = np.zeros(len(x), dtype=np.int64)
+    rc = lib.oracle_pixel_ids(x.ctypes.data, y.ctypes.data, z.ctypes.data, len(x),
+                              int(n_cth), int(n_phi), ids.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_pixel_ids rejected its arguments (rc=%d)" % rc)
+    return ids
+
+
+def pixel_centres(ids, n_cth: int, n_phi: int):
+    """Centres (x, y, z) of the pixels ``ids`` as FP64 unit vectors."""
+    lib = _load()
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    out = [np.zeros(len(ids)) for _ in range(3)]
+    rc = lib.oracle_pixel_centres(ids.ctypes.data, len(ids), int(n_cth), int(n_phi),
+                                  *[o.ctypes.data for o in out])
+    if rc != 0:
+        raise ValueError("oracle_pixel_centres rejected its arguments (rc=%d)" % rc)
+    return out
+
+
+class PixelMap:
+    """Non-empty pixels of a catalog in ascending id order: ``ids`` (int64),
+    ``counts`` (uint32 occupancy) and the centre coordinates ``x, y, z``."""
+
+    def __init__(self, ids, counts, n_cth, n_phi):
+        self.ids = ids
+        self.counts = counts
+        self.n_cth, self.n_phi = n_cth, n_phi
+        self.x, self.y, self.z = pixel_centres(ids, n_cth, n_phi)
+
+    def __len__(self):
+        return len(self.ids)
+
+
+def pixel_map(cat, n_cth: int, n_phi: int) -> PixelMap:
+    ids, counts = np.unique(pixel_ids(cat, n_cth, n_phi), return_counts=True)
+    return PixelMap(ids, counts.astype(np.uint32), n_cth, n_phi)
+
+
+def count_weighted(a, wa, b, wb, binning: Binning, nthreads: int | None = None):
+    """Weighted pair counts (uint64): each pair adds ``wa[i] * wb[j]``.
+    ``b is None``: autocorrelation of ``a`` (pairs i < j plus the
+    ``wa[i] (wa[i] - 1) / 2`` pairs inside each pixel, at zero separation)."""
+    lib = _load()
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    is_auto = b is None
+    if is_auto:
+        b, wb = a, wa
+    xa, ya, za = _xyz(a)
+    xb, yb, zb = _xyz(b)
+    wa = np.ascontiguousarray(wa, dtype=np.uint32)
+    wb = np.ascontiguousarray(wb, dtype=np.uint32)
+    if len(wa) != len(xa) or len(wb) != len(xb):
+        raise ValueError("one weight per point")
+    cb = binning._c()
+    out = np.zeros(lib.oracle_nbins(ctypes.byref(cb)), dtype=np.uint64)
+    rc = lib.oracle_count_weighted(xa.ctypes.data, ya.ctypes.data, za.ctypes.data, wa.ctypes.data,
+                                   len(xa), xb.ctypes.data, yb.ctypes.data, zb.ctypes.data,
+                                   wb.ctypes.data, len(xb), int(is_auto), ctypes.byref(cb),
+                                   int(nthreads), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_count_weighted rejected its arguments (rc=%d)" % rc)
+    return out.reshape(binning.shape)

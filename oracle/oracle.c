@@ -357,3 +357,133 @@ int oracle_count(const double* xa, const double* ya, const double* za, int64_t n
     plan_free(&pl);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pixelised angular correlation (Sec. 3.4, angular correlation function):  */
+/* the catalog is binned into a pixel map and the pixels are correlated,    */
+/* each weighted by the number of objects inside it.                        */
+/*                                                                          */
+/* Pixels are equal-area cells in (cos theta, phi): n_cth rings of equal    */
+/* width in cos theta = z and n_phi sectors of equal width in phi (the      */
+/* pixelisation of Sec. 3.3). Ring and sector are integers decided in FP64  */
+/* by these rules, which the GPU library follows in the same precision:     */
+/*  - ring r = floor((z + 1) * (n_cth / 2)), clamped to [0, n_cth - 1];     */
+/*  - sector k is the one whose boundary rays enclose the point: the point  */
+/*    is on or counter-clockwise of the ray at phi_k = 2 pi k / n_phi and   */
+/*    strictly clockwise of the ray at phi_{k+1}. "Counter-clockwise of the */
+/*    ray with direction (c, s)" is the sign of y*c - x*s, each product and */
+/*    the difference rounded once, with c = cos(phi_k), s = sin(phi_k) from */
+/*    the C library. A point with x^2 + y^2 == 0 (a pole) is in sector 0.   */
+/* The centre of pixel (r, k) is (s_r cos f_k, s_r sin f_k, c_r) with       */
+/* c_r = (2r + 1)/n_cth - 1, s_r = sqrt((1 - c_r)(1 + c_r)) and             */
+/* f_k = 2 pi (k + 1/2) / n_phi. The pixel id is r * n_phi + k.             */
+/* ------------------------------------------------------------------------ */
+static const double OR_TWO_PI = 6.283185307179586476925286766559;
+
+static double ray_side(double x, double y, double c, double s) {
+    double a = y * c;
+    double b = x * s;
+    return a - b;
+}
+
+/* Pixel id of every point; -1 on a bad argument or if a sector search fails. */
+int oracle_pixel_ids(const double* x, const double* y, const double* z, int64_t n,
+                     int n_cth, int n_phi, int64_t* ids) {
+    if (n < 0 || n_cth < 1 || n_phi < 8 || (n > 0 && (!x || !y || !z || !ids))) return -1;
+    double* bc = (double*)malloc(sizeof(double) * (size_t)n_phi);
+    double* bs = (double*)malloc(sizeof(double) * (size_t)n_phi);
+    if (!bc || !bs) { free(bc); free(bs); return -1; }
+    for (int k = 0; k < n_phi; k++) {
+        double a = OR_TWO_PI * (double)k / (double)n_phi;
+        bc[k] = cos(a);
+        bs[k] = sin(a);
+    }
+    int bad = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double t = (z[i] + 1.0) * (0.5 * (double)n_cth);
+        int64_t r = (int64_t)floor(t);
+        if (r < 0) r = 0;
+        if (r > n_cth - 1) r = n_cth - 1;
+        int64_t k = 0;
+        if (x[i] * x[i] + y[i] * y[i] != 0.0) {
+            /* start from the sector of atan2, then step to the enclosing one */
+            double f = atan2(y[i], x[i]);
+            if (f < 0.0) f += OR_TWO_PI;
+            k = (int64_t)floor(f / OR_TWO_PI * (double)n_phi);
+            k = ((k % n_phi) + n_phi) % n_phi;
+            int found = 0;
+            for (int it = 0; it < 4 && !found; it++) {
+                int64_t k1 = (k + 1) % n_phi;
+                if (ray_side(x[i], y[i], bc[k], bs[k]) < 0.0) k = (k + n_phi - 1) % n_phi;
+                else if (ray_side(x[i], y[i], bc[k1], bs[k1]) >= 0.0) k = k1;
+                else found = 1;
+            }
+            if (!found) bad = 1;
+        }
+        ids[i] = r * (int64_t)n_phi + k;
+    }
+    free(bc);
+    free(bs);
+    return bad ? -1 : 0;
+}
+
+/* Centres of the pixels with the given ids (unit vectors, FP64). */
+int oracle_pixel_centres(const int64_t* ids, int64_t n, int n_cth, int n_phi,
+                         double* x, double* y, double* z) {
+    if (n < 0 || n_cth < 1 || n_phi < 8) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        if (ids[i] < 0 || ids[i] >= (int64_t)n_cth * n_phi) return -1;
+        int64_t r = ids[i] / n_phi, k = ids[i] % n_phi;
+        double c = (double)(2 * r + 1) / (double)n_cth - 1.0;
+        double s = sqrt((1.0 - c) * (1.0 + c));
+        double f = OR_TWO_PI * ((double)k + 0.5) / (double)n_phi;
+        x[i] = s * cos(f);
+        y[i] = s * sin(f);
+        z[i] = c;
+    }
+    return 0;
+}
+
+/*
+ * Weighted pair counts: every pair (i, j) adds w_i * w_j to its bin.
+ *  is_auto != 0: pairs i < j of catalog B, plus the w_i (w_i - 1) / 2 pairs of
+ *  objects that share a pixel, which sit at zero separation.
+ *  is_auto == 0: all pairs (i in A, j in B).
+ * Plain double loop (Sec. 3.1). Returns 0, or -1 on a bad argument.
+ */
+int oracle_count_weighted(const double* xa, const double* ya, const double* za,
+                          const uint32_t* wa, int64_t na,
+                          const double* xb, const double* yb, const double* zb,
+                          const uint32_t* wb, int64_t nb,
+                          int is_auto, const or_binning* b, int nthreads, uint64_t* counts) {
+    if (!b || !counts || b->n1 < 1 || nb < 0 || na < 0) return -1;
+    if ((b->kind == OR_RMU || b->kind == OR_SIGMAPI) && (b->n2 < 1 || !b->e2)) return -1;
+    if (b->periodic && !(b->L > 0.0)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    or_plan pl;
+    if (plan_init(&pl, b) != 0) return -1;
+    int nbins = oracle_nbins(b);
+    memset(counts, 0, sizeof(uint64_t) * (size_t)nbins);
+    if (is_auto) { xa = xb; ya = yb; za = zb; wa = wb; na = nb; }
+#pragma omp parallel num_threads(nthreads)
+    {
+        uint64_t* h = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < na; i++) {
+            int64_t j0 = is_auto ? i + 1 : 0;
+            for (int64_t j = j0; j < nb; j++) {
+                int k = classify(&pl, xa[i], ya[i], za[i], xb[j], yb[j], zb[j]);
+                if (k >= 0) h[k] += (uint64_t)wa[i] * (uint64_t)wb[j];
+            }
+            if (is_auto) {
+                int k = classify(&pl, xa[i], ya[i], za[i], xa[i], ya[i], za[i]);
+                if (k >= 0) h[k] += (uint64_t)wa[i] * ((uint64_t)wa[i] - 1u) / 2u;
+            }
+        }
+#pragma omp critical
+        for (int k = 0; k < nbins; k++) counts[k] += h[k];
+        free(h);
+    }
+    plan_free(&pl);
+    return 0;
+}

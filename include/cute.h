@@ -154,6 +154,46 @@ void cute_free_grid(cute_grid* g);
 /* Describe a grid. */
 cute_status cute_get_grid_info(const cute_grid* g, cute_grid_info* info);
 
+/* Pixel map of an angular catalog, for the pixelised angular correlation
+ * (Sec. 3.4, angular correlation function): the objects are binned into
+ * equal-area pixels and every non-empty pixel becomes one point at its
+ * centre whose weight is its occupancy. Counting two pixel maps with
+ * cute_count_pairs adds n_p * n_q per pixel pair, which equals counting the
+ * objects with each one moved to the centre of its pixel.
+ * Pixels (the (cos theta, phi) pixelisation of Sec. 3.3): n_cth rings of
+ * equal width in cos theta = z, n_phi sectors of equal width in phi; pixel id
+ * = ring * n_phi + sector. Both integers are decided in FP64, each operation
+ * rounded once:
+ *   ring   = floor((z + 1) * (0.5 * n_cth)), clamped to [0, n_cth - 1];
+ *   sector = the k with y*c_k - x*s_k >= 0 and y*c_{k+1} - x*s_{k+1} < 0
+ *            (k + 1 taken mod n_phi), where (c_k, s_k) are the C library's
+ *            cos and sin of (2 pi * k) / n_phi; sector 0 when x*x + y*y == 0.
+ * The centre of pixel (r, k) is (s_r cos f_k, s_r sin f_k, c_r) with
+ * c_r = (2r + 1) / n_cth - 1, s_r = sqrt((1 - c_r) * (1 + c_r)),
+ * f_k = (2 pi * (k + 0.5)) / n_phi.
+ * x, y, z: n unit vectors (FP64, |p|^2 within 1e-6 of 1), host or device
+ *   memory as p->device_ptrs says; p->geom must be CUTE_GEOM_SPHERE, and
+ *   p->r_max, cell_size and tile_points grid the centres as cute_build_grid
+ *   does. cute_get_grid_info's n is the number of non-empty pixels.
+ * Counting: a pixel map pairs only with another pixel map, under a THETA
+ *   binning; an autocorrelation adds the n_p (n_p - 1) / 2 object pairs
+ *   inside each pixel to the first bin when edges1[0] == 0 (they sit at zero
+ *   separation). Batched and jackknife counts reject pixel maps.
+ * Synchronous on stream, like cute_build_grid. The map is released with
+ * cute_free_grid.
+ * Errors: CUTE_E_INVALID_ARG for a NULL pointer, n outside [0, 2^31), a
+ * geometry other than SPHERE, n_cth < 1, n_phi < 8, n_cth * n_phi >= 2^31 or
+ * an input that is not a finite unit vector; those of cute_build_grid. */
+cute_status cute_build_pixel_map(const double* x, const double* y, const double* z, int64_t n,
+                                 int32_t n_cth, int32_t n_phi, const cute_grid_params* p,
+                                 void* stream, cute_grid** out);
+
+/* The non-empty pixels of a pixel map in ascending id order: ids[k] and
+ * counts[k] (host memory, cute_get_grid_info's n entries each; either may be
+ * NULL). Waits for stream. Errors: CUTE_E_INVALID_ARG for a grid that is not
+ * a pixel map. */
+cute_status cute_pixel_map_read(const cute_grid* g, uint32_t* ids, uint32_t* counts, void* stream);
+
 /* Pair counts of Sec. 2.2 between grids a and b.
  * b == NULL or b == a: autocorrelation of a (pairs i < j, Sec. 2.2).
  * counts: n1 * max(n2, 1) uint64, row-major with edges1 outer, OVERWRITTEN
@@ -161,7 +201,10 @@ cute_status cute_get_grid_info(const cute_grid* g, cute_grid_info* info);
  * Errors: CUTE_E_INVALID_ARG for bad edges, THETA on a non-SPHERE grid or a
  * 3-D kind on a SPHERE grid, grids of different geometry, a periodic r_max
  * >= L/2 or a periodic grid too coarse for r_max (rebuild it with r_max set);
- * CUTE_E_UNSUPPORTED for SIGMAPI with LOS_Z and MIDPOINT in a periodic box. */
+ * CUTE_E_UNSUPPORTED for SIGMAPI with LOS_Z and MIDPOINT in a periodic box.
+ * Pixel maps (cute_build_pixel_map) are counted with weights: see there;
+ * CUTE_E_INVALID_ARG for a pixel map against a plain grid, CUTE_E_UNSUPPORTED
+ * for a pixel map under a binning other than THETA. */
 cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_binning* bins,
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);

@@ -29,6 +29,7 @@ BATCH_GRAPH, BATCH_EAGER = range(2)
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
             "cute_tune_grid", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched", "cute_count_jackknife",
+            "cute_build_pixel_map", "cute_pixel_map_read",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
 
@@ -125,6 +126,11 @@ def load():
     lib.cute_count_jackknife.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.POINTER(CBinning), ctypes.c_int, vp, vp,
                                          ctypes.POINTER(CountStats), vp]
+    lib.cute_build_pixel_map.restype = ctypes.c_int
+    lib.cute_build_pixel_map.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(GridParams), vp, ctypes.POINTER(vp)]
+    lib.cute_pixel_map_read.restype = ctypes.c_int
+    lib.cute_pixel_map_read.argtypes = [vp, vp, vp, vp]
     lib.cute_xi_estimate.restype = ctypes.c_int
     lib.cute_xi_estimate.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(CBinning), ctypes.c_double, dp]
@@ -283,6 +289,41 @@ def build_grid(pos, geom: int, box_size: float = 0.0, r_max: float = 0.0,
     _check(lib.cute_build_grid(x, y, z, int(n), ctypes.byref(p), _stream_handle(stream),
                                ctypes.byref(h)))
     return Grid(h, int(n), keep if dev else None)
+
+
+class PixelMap(Grid):
+    """A pixel map (cute_build_pixel_map): one point per non-empty pixel, at
+    its centre, weighted by its occupancy. Counted like a SPHERE grid, against
+    another pixel map, with a THETA binning."""
+
+    def __init__(self, handle, n, n_cth, n_phi):
+        super().__init__(handle, n)
+        self.n_cth, self.n_phi = n_cth, n_phi
+
+    def read(self, stream=None):
+        """(ids, counts): the non-empty pixels in ascending id order (ring *
+        n_phi + sector) and their occupancies, as uint32 numpy arrays."""
+        ids = np.zeros(self.n, dtype=np.uint32)
+        cnt = np.zeros(self.n, dtype=np.uint32)
+        _check(load().cute_pixel_map_read(self._h, ids.ctypes.data, cnt.ctypes.data,
+                                          _stream_handle(stream)))
+        return ids, cnt
+
+
+def build_pixel_map(pos, n_cth: int, n_phi: int, r_max: float = 0.0, cell_size: float = 0.0,
+                    stream=None, tile_points: int = 0) -> PixelMap:
+    """cute_build_pixel_map: the pixel map of the unit vectors ``pos`` with
+    ``n_cth`` rings in cos(theta) and ``n_phi`` sectors in phi, gridded for
+    angular counts to ``r_max`` radians."""
+    lib = load()
+    x, y, z, n, dev, keep = _coords(pos)
+    p = GridParams(int(GEOM_SPHERE), 0.0, float(r_max), float(cell_size), int(dev), int(tile_points))
+    h = ctypes.c_void_p()
+    _check(lib.cute_build_pixel_map(x, y, z, int(n), int(n_cth), int(n_phi), ctypes.byref(p),
+                                    _stream_handle(stream), ctypes.byref(h)))
+    g = PixelMap(h, 0, int(n_cth), int(n_phi))
+    g.n = int(g.info().n)
+    return g
 
 
 def tune_grid(pos, geom: int, binning: Binning, box_size: float = 0.0, r_max: float = 0.0,

@@ -101,6 +101,8 @@ cute_status create(const cute_batch_item* items, int32_t n_items, cute_precision
         if ((s = validate_binning(it.bins)) != CUTE_OK) return s;
         const bool is_auto = it.b == nullptr || it.b == it.a;
         const cute_grid* gb = is_auto ? it.a : it.b;
+        if (it.a->h.wt != nullptr || gb->h.wt != nullptr)
+            return fail(CUTE_E_UNSUPPORTED, "item " + std::to_string(i) + ": pixel maps are counted one at a time");
         int g = -1;
         for (size_t k = 0; k < b->groups.size(); k++) {
             const int first = b->groups[k].items[0];

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256, 4) void k_count_batch(BatchArgs BA) {
             tl.end = uni(tp[4 * t + 1]);
             tl.row = uni(tp[4 * t + 2]);
             tl.c0c1 = uni(tp[4 * t + 3]);
-            do_tile<MODE, PREC, EST, true>(P, W, S, B1, B2, T1, T2, lane, tl);
+            do_tile<MODE, PREC, EST, true, false>(P, W, S, B1, B2, T1, T2, lane, tl);
         }
         // the re-test queue refers to this item's points: empty it now
         if (PREC == P_FP32E)

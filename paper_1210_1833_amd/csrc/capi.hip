@@ -85,6 +85,11 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     if (!gb) gb = ga;
     const GridHost& A = ga->h;
     const GridHost& B = gb->h;
+    const bool weighted = A.wt != nullptr || B.wt != nullptr;
+    if (weighted && (A.wt == nullptr || B.wt == nullptr))
+        return fail(CUTE_E_INVALID_ARG, "a pixel map pairs only with another pixel map");
+    if (weighted && bins->kind != CUTE_BIN_THETA)
+        return fail(CUTE_E_UNSUPPORTED, "pixel maps take a THETA binning");
 
     Plan pl;
     plan_binning(bins, pl);
@@ -170,6 +175,8 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     a.tiles = tiles;
     a.ntiles = ntiles;
     a.self = dargs;
+    a.wA = A.wt;
+    a.wB = B.wt;
     CUTE_HIP(hipMemcpyAsync(dargs, &a, sizeof(a), hipMemcpyHostToDevice, hs));
 
     // launch, then the copies, then one wait (the end event is read after it)
@@ -178,6 +185,14 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     if (ntiles > 0) {
         s = launch_count(a, pl.mode, (int)prec, pl.est, kWgWaves, pl.lds, hs, &grid);
         if (s != CUTE_OK) {
+            dfree(tiles, hs);
+            return s;
+        }
+    }
+    // objects that share a pixel: zero separation, in the first bin if it
+    // starts at zero
+    if (weighted && is_auto && bins->edges1[0] == 0.0 && sampled_share == nullptr) {
+        if ((s = add_pixel_self_pairs(A, work, hs)) != CUTE_OK) {
             dfree(tiles, hs);
             return s;
         }

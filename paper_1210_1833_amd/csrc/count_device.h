@@ -405,13 +405,13 @@ struct WaveState {
 // lanes hitting the same bin use different banks. copies is a power of two:
 // word = (bin << log2(copies)) | (lane & (copies - 1)).
 __device__ __forceinline__ void hist_add(unsigned long long* hist, uint32_t bin, int copies,
-                                         int lane, uint32_t w = 1u) {
+                                         int lane, uint64_t w = 1u) {
     const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
     atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], (unsigned long long)w);
 }
 
 // One increment at an LDS byte address (the lane's copy already folded in).
-__device__ __forceinline__ void lds_add(uint32_t byte_addr, uint32_t w) {
+__device__ __forceinline__ void lds_add(uint32_t byte_addr, uint64_t w) {
     __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned long long*)(uintptr_t)byte_addr,
                            (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -421,6 +421,13 @@ __device__ __forceinline__ void lds_add(uint32_t byte_addr, uint32_t w) {
 __device__ __forceinline__ uint32_t pair_weight(const CountArgs& P, uint32_t j) {
     if (P.regs == nullptr) return 1u;
     return P.regs[j] == (uint16_t)P.region ? 1u : 2u;
+}
+
+// Weight of the pair (home i, neighbour j): the product of the two point
+// weights of pixel maps, else the region weight.
+__device__ __forceinline__ uint64_t pair_weight2(const CountArgs& P, uint32_t i, uint32_t j) {
+    if (P.wA != nullptr) return (uint64_t)P.wA[i] * (uint64_t)P.wB[j];
+    return pair_weight(P, j);
 }
 
 // Re-test up to 64 queued pairs per pass, one per lane, through the canonical
@@ -442,7 +449,7 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
             const P64 p = P.A.p64[i];
             const P64 q = P.B.p64[j];
             k = classify_pair64<MODE, EST>(P, T1, T2, p, q);
-            if (k != kNoBin) hist_add(hist, k, P.copies, lane, pair_weight(P, j));
+            if (k != kNoBin) hist_add(hist, k, P.copies, lane, pair_weight2(P, i, j));
             // the FP32-only decision of the same pair, as the main loop made it
             const float4 a = P.A.p32[i];
             const float4 b = P.B.p32[j];
@@ -525,7 +532,19 @@ __device__ __forceinline__ void home_valid(const CountArgs& P, uint32_t h, bool*
     }
 }
 
-template <int MODE, int PREC, int EST, bool PM, bool MASKED, bool LO, uint32_t U>
+// Weights of home points h .. h+U-1 (wave-uniform, scalar loads).
+template <bool WT, uint32_t U>
+__device__ __forceinline__ void home_weights(const CountArgs& P, uint32_t h, uint32_t* hw) {
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) hw[u] = 1u;
+    if (WT) {
+        const cu32p wa = (cu32p)(const void*)P.wA;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) hw[u] = wa[h + u];
+    }
+}
+
+template <int MODE, int PREC, int EST, bool PM, bool WT, bool MASKED, bool LO, uint32_t U>
 __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const Tab32& T,
                                        const float2* B1, const float2* B2, const double* T1,
                                        const double* T2, int lane, bool lvalid, bool lmask,
@@ -542,6 +561,8 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     }
     bool hv[U];
     home_valid<PM, U>(P, h, hv);
+    uint32_t hw[U];
+    home_weights<WT, U>(P, h, hw);
     uint32_t off[U];
     bool cnt[U], amb[U];
 #pragma unroll
@@ -582,7 +603,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) lds_add(off[u], lw);
+        if (cnt[u]) lds_add(off[u], WT ? (uint64_t)lw * hw[u] : (uint64_t)lw);
     if (PREC == P_FP32E && any_amb) {
         // remember the pair for the end of the chunk: bit (home - ts) of this
         // lane's mask, and the home offset in the wave's mask
@@ -595,7 +616,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     }
 }
 
-template <int MODE, int EST, bool PM, bool MASKED, bool SHIFTED, uint32_t U>
+template <int MODE, int EST, bool PM, bool WT, bool MASKED, bool SHIFTED, uint32_t U>
 __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const double* T1,
                                        const double* T2, int lane, bool lvalid, bool lmask,
                                        uint32_t lj, double qx, double qy, double qz, double sx, double sy,
@@ -610,6 +631,8 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     }
     bool hv[U];
     home_valid<PM, U>(P, h, hv);
+    uint32_t hw[U];
+    home_weights<WT, U>(P, h, hw);
     uint32_t bin[U];
     bool cnt[U];
 #pragma unroll
@@ -655,7 +678,7 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane, lw);
+        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane, WT ? (uint64_t)lw * hw[u] : (uint64_t)lw);
 }
 
 // The chunk being assembled from neighbour spans (per-lane fields in VGPRs,
@@ -669,7 +692,7 @@ struct Chunk {
     bool lmask;        // per lane: j > i test applies
 };
 
-template <int MODE, int PREC, int EST, bool PM>
+template <int MODE, int PREC, int EST, bool PM, bool WT>
 __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
                           const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
                           uint32_t te) {
@@ -677,7 +700,7 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     bool lvalid = (uint32_t)lane < C.filled;
     // a neighbour excluded by the point mask leaves its lane idle
     if (PM && P.mbB != nullptr && lvalid) lvalid = ((P.mbB[C.lj >> 5] >> (C.lj & 31u)) & 1u) == 0u;
-    const uint32_t lw = lvalid ? pair_weight(P, C.lj) : 1u;
+    const uint32_t lw = lvalid ? (WT ? P.wB[C.lj] : pair_weight(P, C.lj)) : 1u;
     if (PREC == P_FP64) {
         double qx = 0.0, qy = 0.0, qz = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
         if (lvalid) {
@@ -693,10 +716,10 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     {                                                                                           \
         uint32_t h = ts;                                                                        \
         for (; h + U <= te; h += U)                                                             \
-            step64<MODE, EST, PM, MSK, SH, U>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
+            step64<MODE, EST, PM, WT, MSK, SH, U>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
                                           sx, sy, sz, lw, h);                                   \
         for (; h < te; h++)                                                                     \
-            step64<MODE, EST, PM, MSK, SH, 1>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
+            step64<MODE, EST, PM, WT, MSK, SH, 1>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
                                           sx, sy, sz, lw, h);                                   \
     }
         if (C.masked) {
@@ -727,11 +750,11 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     {                                                                                              \
         uint32_t h = ts;                                                                           \
         for (; h + U <= te; h += U)                                                                \
-            step32<MODE, PREC, EST, PM, MSK, LOW, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
+            step32<MODE, PREC, EST, PM, WT, MSK, LOW, U>(P, W, tab, B1, B2, T1, T2, lane, lvalid,  \
                                                      C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
                                                      qlz, lb, lw, ts, ambh, hsum, h);              \
         for (; h < te; h++)                                                                        \
-            step32<MODE, PREC, EST, PM, MSK, LOW, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid,      \
+            step32<MODE, PREC, EST, PM, WT, MSK, LOW, 1>(P, W, tab, B1, B2, T1, T2, lane, lvalid,  \
                                                      C.lmask, C.lj, C.lcode, qx, qy, qz, qlx, qly, \
                                                      qlz, lb, lw, ts, ambh, hsum, h);              \
     }
@@ -757,7 +780,7 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
 
 // Append the neighbour span [a0, a1) (image code, j > i test) to the chunk,
 // running every chunk that fills up.
-template <int MODE, int PREC, int EST, bool PM>
+template <int MODE, int PREC, int EST, bool PM, bool WT>
 __device__ void feed(const CountArgs& P, WaveState& W, const float2* B1, const float2* B2,
                      const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
                      uint32_t te, uint32_t a0, uint32_t a1, uint32_t code, bool masked) {
@@ -784,7 +807,7 @@ __device__ void feed(const CountArgs& P, WaveState& W, const float2* B1, const f
         C.masked = C.masked | masked;
         C.shifted = C.shifted | (code != kNoShift);
         a0 += take;
-        if (C.filled == 64u) run_chunk<MODE, PREC, EST, PM>(P, W, B1, B2, T1, T2, lane, C, ts, te);
+        if (C.filled == 64u) run_chunk<MODE, PREC, EST, PM, WT>(P, W, B1, B2, T1, T2, lane, C, ts, te);
     }
 }
 
@@ -1032,7 +1055,7 @@ __device__ bool gen_spans(const CountArgs& P, const Tile& tl, int lane, SpanBuf&
 
 // Count the pairs of one home tile: spans are generated into the LDS span
 // buffer, then fed chunk by chunk to the hot loop.
-template <int MODE, int PREC, int EST, bool PM>
+template <int MODE, int PREC, int EST, bool PM, bool WT>
 __device__ void do_tile(const CountArgs& P, WaveState& W, SpanBuf& S, const float2* B1,
                         const float2* B2, const double* T1, const double* T2, int lane,
                         const Tile& tl) {
@@ -1050,11 +1073,11 @@ __device__ void do_tile(const CountArgs& P, WaveState& W, SpanBuf& S, const floa
         done = gen_spans(P, tl, lane, S, &row);
         for (uint32_t k = 0; k < S.n; k++) {
             const uint32_t a0 = uni(S.a[k]), a1 = uni(S.b[k]), f = uni(S.f[k]);
-            feed<MODE, PREC, EST, PM>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end, a0, a1,
+            feed<MODE, PREC, EST, PM, WT>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end, a0, a1,
                                   f & 0xffu, (f & 0x100u) != 0u);
         }
     }
-    if (C.filled) run_chunk<MODE, PREC, EST, PM>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end);
+    if (C.filled) run_chunk<MODE, PREC, EST, PM, WT>(P, W, B1, B2, T1, T2, lane, C, tl.start, tl.end);
 }
 
 

@@ -28,7 +28,8 @@ namespace cute {
 namespace {
 
 // Four 4-wave workgroups per CU: the register budget stays at 128 VGPRs.
-template <int MODE, int PREC, int EST>
+// WT: pixel maps, each pair weighted by the product of the point weights.
+template <int MODE, int PREC, int EST, bool WT>
 __global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
         tl.end = uni(tp[4 * t + 1]);
         tl.row = uni(tp[4 * t + 2]);
         tl.c0c1 = uni(tp[4 * t + 3]);
-        do_tile<MODE, PREC, EST, false>(P, W, S, B1, B2, T1, T2, lane, tl);
+        do_tile<MODE, PREC, EST, false, WT>(P, W, S, B1, B2, T1, T2, lane, tl);
     }
     if (PREC == P_FP32E)
         W.tail = drain_queue<MODE, EST>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,
@@ -100,9 +101,9 @@ __global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
     }
 }
 
-template <int MODE, int PREC, int EST>
+template <int MODE, int PREC, int EST, bool WT>
 cute_status launch_one(const CountArgs& a, int wg_waves, size_t lds, hipStream_t s, int* grid_used) {
-    auto kern = k_count<MODE, PREC, EST>;
+    auto kern = k_count<MODE, PREC, EST, WT>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -110,12 +111,12 @@ cute_status launch_one(const CountArgs& a, int wg_waves, size_t lds, hipStream_t
     }
     // occupancy of this variant at this LDS size, queried once per device
     static std::mutex mu;
-    static std::map<std::tuple<int, int, size_t>, std::pair<int, int>> cache;
+    static std::map<std::tuple<int, int, size_t, bool>, std::pair<int, int>> cache;
     int dev = 0, ncu = 0, per_cu = 0;
     CUTE_HIP(hipGetDevice(&dev));
     {
         std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(std::make_tuple(dev, wg_waves, lds));
+        auto it = cache.find(std::make_tuple(dev, wg_waves, lds, WT));
         if (it != cache.end()) {
             ncu = it->second.first;
             per_cu = it->second.second;
@@ -126,7 +127,7 @@ cute_status launch_one(const CountArgs& a, int wg_waves, size_t lds, hipStream_t
         CUTE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wg_waves, lds));
         if (per_cu < 1) per_cu = 1;
         std::lock_guard<std::mutex> lk(mu);
-        cache[std::make_tuple(dev, wg_waves, lds)] = std::make_pair(ncu, per_cu);
+        cache[std::make_tuple(dev, wg_waves, lds, WT)] = std::make_pair(ncu, per_cu);
     }
     int64_t want = (int64_t)per_cu * ncu;
     int64_t need = ((int64_t)a.ntiles + wg_waves - 1) / wg_waves;
@@ -141,8 +142,17 @@ cute_status launch_one(const CountArgs& a, int wg_waves, size_t lds, hipStream_t
 template <int MODE, int PREC>
 cute_status launch_est(const CountArgs& a, int est, int wg_waves, size_t lds, hipStream_t s,
                        int* g) {
-    if (est == E_LOG) return launch_one<MODE, PREC, E_LOG>(a, wg_waves, lds, s, g);
-    return launch_one<MODE, PREC, E_LIN>(a, wg_waves, lds, s, g);
+    if (a.wA != nullptr) {
+        // weighted pairs: the angular kernels only (pixel maps)
+        if constexpr (MODE == M_THETA) {
+            if (est == E_LOG) return launch_one<MODE, PREC, E_LOG, true>(a, wg_waves, lds, s, g);
+            return launch_one<MODE, PREC, E_LIN, true>(a, wg_waves, lds, s, g);
+        } else {
+            return fail(CUTE_E_UNSUPPORTED, "weighted pairs need a THETA binning");
+        }
+    }
+    if (est == E_LOG) return launch_one<MODE, PREC, E_LOG, false>(a, wg_waves, lds, s, g);
+    return launch_one<MODE, PREC, E_LIN, false>(a, wg_waves, lds, s, g);
 }
 
 template <int MODE>

@@ -120,6 +120,10 @@ struct CountArgs {
     // excluded; nullptr = no mask
     const uint32_t* mbA;
     const uint32_t* mbB;
+    // point weights of two pixel maps (sorted order): each pair adds
+    // wA[i] * wB[j]; nullptr for unweighted catalogs
+    const uint32_t* wA;
+    const uint32_t* wB;
 };
 
 // A batched launch: the items (one CountArgs each, in device memory) share
@@ -153,6 +157,13 @@ struct GridHost {
     uint32_t* cstart;
     void* block;         // the one device allocation holding p64, p32 and cstart
     int tile_max;        // most points in a home tile (1..64)
+    // pixel maps: occupancy of each point in sorted order, and the non-empty
+    // pixels (ids ascending) with their occupancies, all in one allocation
+    uint32_t* wt;        // nullptr for plain catalogs
+    uint32_t* pix_id;
+    uint32_t* pix_n;
+    void* wblock;
+    int n_cth, n_phi;
     double ms_build;
     GridView view() const;
 };
@@ -221,6 +232,9 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
                         hipStream_t s);
 
 // persistent count launch; *grid_used receives the number of workgroups
+// Add the pairs of objects that share a pixel of a pixel map to *bin.
+cute_status add_pixel_self_pairs(const GridHost& g, unsigned long long* bin, hipStream_t s);
+
 cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int wg_waves,
                          size_t lds_bytes, hipStream_t stream, int* grid_used);
 

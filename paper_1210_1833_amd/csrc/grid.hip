@@ -472,6 +472,7 @@ extern "C" void cute_free_grid(cute_grid* g) {
     // the buffers come from the stream-ordered pool; the caller guarantees
     // that no work on any stream still uses the grid
     dfree(g->h.block, nullptr);
+    dfree(g->h.wblock, nullptr);
     delete g;
 }
 

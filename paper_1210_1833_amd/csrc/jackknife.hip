@@ -77,6 +77,7 @@ extern "C" cute_status cute_count_jackknife(const cute_grid* grid, const int32_t
     if (prec != CUTE_PREC_FP64 && prec != CUTE_PREC_FP32_EDGE && prec != CUTE_PREC_FP32_ONLY)
         return fail(CUTE_E_INVALID_ARG, "unknown precision");
     const GridHost& G = grid->h;
+    if (G.wt != nullptr) return fail(CUTE_E_UNSUPPORTED, "pixel maps have no jackknife pass");
     if (G.geom == CUTE_GEOM_SPHERE)
         return fail(CUTE_E_UNSUPPORTED, "jackknife regions need a 3-D grid");
     hipStream_t hs = (hipStream_t)stream;

@@ -170,3 +170,25 @@ def test_jackknife_rejects_bad_arguments(lib):
                                     out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG
     assert lib.cute_count_jackknife(fake, None, 0, 4, ctypes.byref(b), 1,
                                     out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG
+
+
+def test_pixel_map_rejects_bad_arguments(lib):
+    x = np.zeros(4)
+    X = (x.ctypes.data, x.ctypes.data, x.ctypes.data)
+    h = ctypes.c_void_p()
+    ps = cute.GridParams(cute.GEOM_SPHERE, 0.0, 0.1, 0.0, 0, 0)
+    pb = cute.GridParams(cute.GEOM_BOX_OPEN, 0.0, 0.1, 0.0, 0, 0)
+    bad = [
+        (X, 4, 16, 32, pb),                  # not SPHERE
+        (X, 4, 0, 32, ps),                   # no rings
+        (X, 4, 16, 7, ps),                   # fewer than 8 sectors
+        (X, 4, 65536, 32768, ps),            # ids would not fit
+        (X, -1, 16, 32, ps),                 # negative size
+        ((None, None, None), 4, 16, 32, ps),  # NULL coordinates
+    ]
+    for xyz, n, nc, nph, p in bad:
+        assert lib.cute_build_pixel_map(*xyz, n, nc, nph, ctypes.byref(p), None,
+                                        ctypes.byref(h)) == cute.E_INVALID_ARG
+    assert lib.cute_build_pixel_map(*X, 4, 16, 32, None, None, ctypes.byref(h)) == cute.E_INVALID_ARG
+    assert lib.cute_build_pixel_map(*X, 4, 16, 32, ctypes.byref(ps), None, None) == cute.E_INVALID_ARG
+    assert lib.cute_pixel_map_read(None, None, None, None) == cute.E_INVALID_ARG

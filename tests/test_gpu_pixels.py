@@ -1,0 +1,203 @@
+"""GPU parity of the pixelised angular correlation (Sec. 3.4, angular
+correlation function): pixel maps built by the HIP library against the
+oracle's pixel maps (ids and occupancies, bit-exact), and weighted pair
+counts of pixel maps against the oracle's weighted counts (bit-exact for FP64
+and FP32_EDGE), from small maps that span many tiles to the 5e-3 sq-deg maps
+of the paper's Table 2 catalogs."""
+import sys
+
+import numpy as np
+import pytest
+
+import catalogs
+import oracle
+import paper_1210_1833_amd as cute
+
+pytestmark = pytest.mark.gpu
+
+EXACT = [cute.PREC_FP64, cute.PREC_FP32_EDGE]
+# 2048 rings x 4028 sectors: pixels of 4 pi / (2048 * 4028) sr = 5.0e-3 sq-deg
+TABLE2_PIX = (2048, 4028)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    cute.load()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cap(n, half_deg, seed, dec0=20.0, blobs=0, sigma_deg=0.3):
+    """Unit vectors in a cap (uniform, or Gaussian blobs of sigma_deg)."""
+    rng = np.random.default_rng(seed)
+    c = np.deg2rad(dec0)
+    axis = np.array([np.cos(c), 0.0, np.sin(c)])
+    if blobs:
+        centres = cap(blobs, half_deg, seed + 1, dec0)
+        v = np.repeat(centres, n // blobs, axis=0)
+        v = v + rng.normal(scale=np.deg2rad(sigma_deg), size=v.shape)
+    else:
+        ct = rng.uniform(np.cos(np.deg2rad(half_deg)), 1.0, n)
+        ph = rng.uniform(0, 2 * np.pi, n)
+        st = np.sqrt(1 - ct * ct)
+        loc = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=1)
+        # rotate the z axis onto the cap axis
+        z = np.array([0.0, 0.0, 1.0])
+        k = np.cross(z, axis)
+        s, cc = np.linalg.norm(k), z @ axis
+        k = k / s
+        K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+        R = np.eye(3) + s * K + (1 - cc) * K @ K
+        v = loc @ R.T
+    return v / np.linalg.norm(v, axis=1)[:, None]
+
+
+def awkward_points():
+    """Poles, axis points (on sector boundaries), ring boundaries and the
+    equator."""
+    pts = [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0],
+           [np.sqrt(0.5), np.sqrt(0.5), 0.0], [-np.sqrt(0.5), np.sqrt(0.5), 0.0]]
+    for z in (-0.5, 0.0, 0.5, 0.75):
+        s = np.sqrt(1 - z * z)
+        pts += [[s, 0.0, z], [0.0, -s, z], [-s, 0.0, z]]
+    return np.array(pts, dtype=np.float64)
+
+
+@pytest.mark.parametrize("n_cth,n_phi", [(16, 8), (64, 96), (333, 1001), TABLE2_PIX])
+def test_pixel_map_matches_oracle(n_cth, n_phi):
+    v = np.random.default_rng(5).normal(size=(40000, 3))
+    v = v / np.linalg.norm(v, axis=1)[:, None]
+    v = np.concatenate([v, awkward_points(), cap(20000, 3.0, 6)])
+    say("pixel map %d x %d of %d points" % (n_cth, n_phi, len(v)))
+    want = oracle.pixel_map(v, n_cth, n_phi)
+    g = cute.build_pixel_map(v, n_cth, n_phi, r_max=np.deg2rad(2.0))
+    ids, cnt = g.read()
+    np.testing.assert_array_equal(ids.astype(np.int64), want.ids)
+    np.testing.assert_array_equal(cnt, want.counts)
+    assert g.n == len(want)
+
+
+def test_pixel_map_from_device_memory():
+    import torch
+    v = cap(30000, 5.0, 7, blobs=300)
+    want = oracle.pixel_map(v, 512, 1024)
+    t = torch.from_numpy(v).cuda()
+    g = cute.build_pixel_map((t[:, 0].contiguous(), t[:, 1].contiguous(), t[:, 2].contiguous()),
+                             512, 1024, r_max=np.deg2rad(2.0))
+    ids, cnt = g.read()
+    np.testing.assert_array_equal(ids.astype(np.int64), want.ids)
+    np.testing.assert_array_equal(cnt, want.counts)
+
+
+def test_empty_pixel_map_counts_nothing():
+    e = np.zeros((0, 3))
+    g = cute.build_pixel_map(e, 64, 64, r_max=0.1)
+    assert g.n == 0
+    h = cute.build_pixel_map(cap(100, 2.0, 8), 64, 64, r_max=0.1)
+    bn = cute.Binning(cute.BIN_THETA, np.linspace(0.0, 0.1, 5))
+    for prec in EXACT:
+        assert not cute.count_pairs(g, None, bn, prec).any()
+        assert not cute.count_pairs(g, h, bn, prec).any()
+
+
+def wpix_case(d, r, n_cth, n_phi, edges, precs=EXACT):
+    bn = cute.Binning(cute.BIN_THETA, edges)
+    ob = oracle.Binning(oracle.THETA, edges)
+    od, orr = oracle.pixel_map(d, n_cth, n_phi), oracle.pixel_map(r, n_cth, n_phi)
+    gd = cute.build_pixel_map(d, n_cth, n_phi, r_max=edges[-1])
+    gr = cute.build_pixel_map(r, n_cth, n_phi, r_max=edges[-1])
+    want_dd = oracle.count_weighted(od, od.counts, None, None, ob)
+    want_dr = oracle.count_weighted(od, od.counts, orr, orr.counts, ob)
+    assert want_dd.sum() > 0 and want_dr.sum() > 0
+    for prec in precs:
+        np.testing.assert_array_equal(cute.count_pairs(gd, None, bn, prec), want_dd,
+                                      err_msg="DD prec %d" % prec)
+        np.testing.assert_array_equal(cute.count_pairs(gd, gr, bn, prec), want_dr,
+                                      err_msg="DR prec %d" % prec)
+    return gd, gr, bn
+
+
+@pytest.mark.parametrize("e0", [0.0, 0.02])
+def test_weighted_counts_match_oracle_linear(e0):
+    """Clustered data and uniform randoms in a 6-degree cap, 0.1-degree
+    pixels (thousands of pixels, many tiles), linear theta bins to 4 deg;
+    e0 = 0 puts the same-pixel pairs in the first bin."""
+    d = cap(40000, 6.0, 9, blobs=400)
+    r = cap(60000, 6.0, 10)
+    say("w_pix linear, e0 = %g" % e0)
+    wpix_case(d, r, 1800, 3600, np.linspace(e0, np.deg2rad(4.0), 21))
+
+
+def test_weighted_counts_match_oracle_log():
+    """Log theta bins (the other bin estimator), 0.05-degree pixels."""
+    d = cap(30000, 4.0, 11, blobs=300, sigma_deg=0.1)
+    r = cap(30000, 4.0, 12)
+    say("w_pix log bins")
+    wpix_case(d, r, 3600, 7200, np.deg2rad(0.05 * 10.0 ** (np.arange(25) / 12.0)))
+
+
+def test_weighted_fp32_only_is_close():
+    d = cap(20000, 5.0, 13, blobs=200)
+    bn = cute.Binning(cute.BIN_THETA, np.deg2rad(np.linspace(0.0, 3.0, 31)))
+    g = cute.build_pixel_map(d, 1800, 3600, r_max=bn.edges1[-1])
+    c64 = cute.count_pairs(g, None, bn, cute.PREC_FP64).astype(float)
+    c32 = cute.count_pairs(g, None, bn, cute.PREC_FP32_ONLY).astype(float)
+    assert abs(c32.sum() - c64.sum()) <= 1e-3 * c64.sum()
+
+
+def test_wpix_table2_full_size():
+    """The Table 2 w_pix configuration: 3e5 data and 3e5 randoms of the
+    light-cone subset, pixels of 5e-3 sq-deg, 256 linear theta bins to 30
+    deg. FP32_EDGE equals FP64 for DD and DR; the DR rows of 64 sampled data
+    pixels (their objects mapped alone) equal the oracle's."""
+    d3, r3 = catalogs.table2()
+    d, r = catalogs.unit_vectors(d3).stacked(), catalogs.unit_vectors(r3).stacked()
+    e = np.deg2rad(np.linspace(0.0, 30.0, 257))
+    bn = cute.Binning(cute.BIN_THETA, e)
+    gd = cute.build_pixel_map(d, *TABLE2_PIX, r_max=e[-1])
+    gr = cute.build_pixel_map(r, *TABLE2_PIX, r_max=e[-1])
+    say("w_pix Table 2: %d data pixels, %d random pixels" % (gd.n, gr.n))
+    for name, b in (("DD", None), ("DR", gr)):
+        c32 = cute.count_pairs(gd, b, bn, cute.PREC_FP32_EDGE)
+        c64 = cute.count_pairs(gd, b, bn, cute.PREC_FP64)
+        np.testing.assert_array_equal(c32, c64, err_msg=name)
+    tot = cute.count_pairs(gd, gr, bn, cute.PREC_FP32_EDGE)
+    assert int(tot.sum()) == len(d) * len(r)  # every pair is within 30 deg
+    ids = oracle.pixel_ids(d, *TABLE2_PIX)
+    pick = np.random.default_rng(61).choice(np.unique(ids), 64, replace=False)
+    sub = d[np.isin(ids, pick)]
+    gs = cute.build_pixel_map(sub, *TABLE2_PIX, r_max=e[-1])
+    os_, orr = oracle.pixel_map(sub, *TABLE2_PIX), oracle.pixel_map(r, *TABLE2_PIX)
+    want = oracle.count_weighted(os_, os_.counts, orr, orr.counts, oracle.Binning(oracle.THETA, e))
+    for prec in EXACT:
+        np.testing.assert_array_equal(cute.count_pairs(gs, gr, bn, prec), want,
+                                      err_msg="sampled rows, prec %d" % prec)
+
+
+def test_pixel_maps_are_rejected_where_unsupported():
+    v = cap(2000, 3.0, 14)
+    pm = cute.build_pixel_map(v, 256, 512, r_max=0.05)
+    plain = cute.build_grid(v, cute.GEOM_SPHERE, r_max=0.05)
+    th = cute.Binning(cute.BIN_THETA, np.linspace(0.0, 0.05, 6))
+    with pytest.raises(cute.CuteError) as e:
+        cute.count_pairs(pm, plain, th)
+    assert e.value.status == cute.E_INVALID_ARG
+    with pytest.raises(cute.CuteError) as e:
+        cute.count_pairs(pm, None, cute.Binning(cute.BIN_MONO, np.linspace(0.0, 0.05, 6)))
+    assert e.value.status in (cute.E_INVALID_ARG, cute.E_UNSUPPORTED)
+    with pytest.raises(cute.CuteError) as e:
+        cute.count_pairs_batched([cute.BatchItem(pm, None, th)])
+    assert e.value.status == cute.E_UNSUPPORTED
+    with pytest.raises(cute.CuteError) as e:
+        cute.count_jackknife(pm, np.zeros(pm.n, dtype=np.int32), 2, th)
+    assert e.value.status == cute.E_UNSUPPORTED
+    with pytest.raises(cute.CuteError) as e:
+        cute.build_pixel_map(v * 2.0, 64, 64)
+    assert e.value.status == cute.E_INVALID_ARG

@@ -10,6 +10,8 @@ GPU library.
 * ``pixel_map`` and ``count_weighted``: the pixelised angular correlation
   (Sec. 3.4): objects binned into equal-area (cos theta, phi) pixels, and pair
   counts in which each pixel carries its occupancy as a weight.
+* ``count_radial``: the radial correlation (Sec. 2.1 and 3.4): pairs within
+  an angular aperture, binned by their redshift difference.
 * ``estimators``: the natural, Landy-Szalay and periodic-box estimators of
   Sec. 2.2 and the Legendre multipoles of Sec. 2.1, in exact rational
   arithmetic.
@@ -84,6 +86,11 @@ def _load():
             lib.oracle_pixel_centres.restype = ctypes.c_int
             lib.oracle_pixel_centres.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                                  ctypes.c_int] + [ctypes.c_void_p] * 3
+            lib.oracle_count_radial.restype = ctypes.c_int
+            lib.oracle_count_radial.argtypes = (
+                [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
+                + [ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                   ctypes.c_int, ctypes.c_void_p])
             lib.oracle_count_weighted.restype = ctypes.c_int
             lib.oracle_count_weighted.argtypes = (
                 [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
@@ -246,3 +253,28 @@ def count_weighted(a, wa, b, wb, binning: Binning, nthreads: int | None = None):
     if rc != 0:
         raise ValueError("oracle_count_weighted rejected its arguments (rc=%d)" % rc)
     return out.reshape(binning.shape)
+
+
+def count_radial(a, ra, b, rb, aperture: float, edges, nthreads: int | None = None):
+    """Radial pair counts (uint64, one per bin of ``edges``): pairs of unit
+    vectors closer than ``aperture`` radians, binned by |ra[i] - rb[j]|.
+    ``b is None``: autocorrelation of ``a`` (pairs i < j)."""
+    lib = _load()
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    is_auto = b is None
+    if is_auto:
+        b, rb = a, ra
+    xa, ya, za = _xyz(a)
+    xb, yb, zb = _xyz(b)
+    ra, rb, e = _f64(ra), _f64(rb), _f64(edges)
+    if len(ra) != len(xa) or len(rb) != len(xb):
+        raise ValueError("one redshift per point")
+    out = np.zeros(len(e) - 1, dtype=np.uint64)
+    rc = lib.oracle_count_radial(xa.ctypes.data, ya.ctypes.data, za.ctypes.data, ra.ctypes.data,
+                                 len(xa), xb.ctypes.data, yb.ctypes.data, zb.ctypes.data,
+                                 rb.ctypes.data, len(xb), int(is_auto), float(aperture),
+                                 len(e) - 1, e.ctypes.data, int(nthreads), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_count_radial rejected its arguments (rc=%d)" % rc)
+    return out

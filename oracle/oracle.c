@@ -487,3 +487,46 @@ int oracle_count_weighted(const double* xa, const double* ya, const double* za,
     plan_free(&pl);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Radial correlation (Sec. 2.1, the radial 2PCF; Sec. 3.4): pairs of       */
+/* objects aligned with the line of sight, i.e. subtending an angle theta   */
+/* below the aperture, binned by the difference of their redshifts.         */
+/* The angle is tested through the chord as in the angular case:            */
+/* theta < aperture  <=>  c^2 < (2 sin(aperture / 2))^2, with c^2 formed    */
+/* from the FP64 differences of the unit vectors. The redshift difference   */
+/* dz = |z_i - z_j| (one rounding) falls in bin k when e_k <= dz < e_{k+1}. */
+/* ------------------------------------------------------------------------ */
+int oracle_count_radial(const double* xa, const double* ya, const double* za, const double* ra,
+                        int64_t na, const double* xb, const double* yb, const double* zb,
+                        const double* rb, int64_t nb, int is_auto, double aperture, int nbins,
+                        const double* edges, int nthreads, uint64_t* counts) {
+    if (!counts || !edges || nbins < 1 || na < 0 || nb < 0 || !(aperture > 0.0)) return -1;
+    for (int k = 0; k < nbins; k++)
+        if (!(edges[k] < edges[k + 1]) || edges[k] < 0.0) return -1;
+    if (nthreads < 1) nthreads = 1;
+    const double c = 2.0 * sin(0.5 * aperture);
+    const double t_ap = c * c;
+    memset(counts, 0, sizeof(uint64_t) * (size_t)nbins);
+    if (is_auto) { xa = xb; ya = yb; za = zb; ra = rb; na = nb; }
+#pragma omp parallel num_threads(nthreads)
+    {
+        uint64_t* h = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < na; i++) {
+            int64_t j0 = is_auto ? i + 1 : 0;
+            for (int64_t j = j0; j < nb; j++) {
+                double dx = xa[i] - xb[j], dy = ya[i] - yb[j], dz = za[i] - zb[j];
+                double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (!(d2 < t_ap)) continue;
+                double dr = fabs(ra[i] - rb[j]);
+                if (!(edges[0] <= dr && dr < edges[nbins])) continue;
+                h[last_le(edges, nbins, dr)]++;
+            }
+        }
+#pragma omp critical
+        for (int k = 0; k < nbins; k++) counts[k] += h[k];
+        free(h);
+    }
+    return 0;
+}

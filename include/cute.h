@@ -209,6 +209,30 @@ cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);
 
+/* Radial correlation counts (Sec. 2.1, the radial 2PCF; Sec. 3.4): the pairs
+ * of objects aligned with the line of sight, i.e. subtending an angle below
+ * the aperture, binned by the difference of their redshifts.
+ * a, b: SPHERE grids of unit vectors (b == NULL or b == a: autocorrelation of
+ *   a, pairs i < j); build them with r_max >= aperture for a tight stencil.
+ * ra, rb: one redshift per object, in the order the coordinates were given to
+ *   cute_build_grid (host or device memory as r_on_device says; rb unused for
+ *   an autocorrelation); finite.
+ * aperture: radians in (0, pi]; a pair is aligned when its chord^2, formed
+ *   from the FP64 differences of the unit vectors, is below
+ *   (2 sin(aperture / 2))^2, i.e. theta < aperture.
+ * edges: n_bins + 1 finite, non-negative, strictly increasing redshift
+ *   differences; a pair with dz = |r_i - r_j| (one FP64 subtraction) is
+ *   counted in bin k when edges[k] <= dz < edges[k + 1].
+ * counts: n_bins uint64, OVERWRITTEN (a device pointer if counts_on_device).
+ * FP64 throughout: few pairs fall inside an aperture, so no FP32 path.
+ * Errors: CUTE_E_INVALID_ARG for NULL pointers, bad edges or aperture,
+ * non-SPHERE grids or non-finite redshifts; CUTE_E_UNSUPPORTED for pixel
+ * maps; those of cute_count_pairs otherwise. */
+cute_status cute_count_radial(const cute_grid* a, const double* ra, const cute_grid* b,
+                              const double* rb, int32_t r_on_device, double aperture,
+                              int32_t n_bins, const double* edges, uint64_t* counts,
+                              int32_t counts_on_device, cute_count_stats* st, void* stream);
+
 /* Choose the cell side and the home-tile size of a grid by measurement. The
  * best cell side is data dependent (Sec. 3.3), so each candidate pair is
  * timed: a grid of n points (x, y, z, read as for cute_build_grid with

@@ -29,7 +29,7 @@ BATCH_GRAPH, BATCH_EAGER = range(2)
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
             "cute_tune_grid", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched", "cute_count_jackknife",
-            "cute_build_pixel_map", "cute_pixel_map_read",
+            "cute_build_pixel_map", "cute_pixel_map_read", "cute_count_radial",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
 
@@ -131,6 +131,10 @@ def load():
                                          ctypes.POINTER(GridParams), vp, ctypes.POINTER(vp)]
     lib.cute_pixel_map_read.restype = ctypes.c_int
     lib.cute_pixel_map_read.argtypes = [vp, vp, vp, vp]
+    lib.cute_count_radial.restype = ctypes.c_int
+    lib.cute_count_radial.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int32, dp, vp, ctypes.c_int32,
+                                      ctypes.POINTER(CountStats), vp]
     lib.cute_xi_estimate.restype = ctypes.c_int
     lib.cute_xi_estimate.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(CBinning), ctypes.c_double, dp]
@@ -324,6 +328,42 @@ def build_pixel_map(pos, n_cth: int, n_phi: int, r_max: float = 0.0, cell_size: 
     g = PixelMap(h, 0, int(n_cth), int(n_phi))
     g.n = int(g.info().n)
     return g
+
+
+def _values(v):
+    """(pointer, on_device, keepalive) of a float64 array: a torch device
+    tensor or anything numpy takes."""
+    if hasattr(v, "is_cuda") and v.is_cuda:
+        import torch
+        t = v.to(torch.float64).contiguous()
+        return t.data_ptr(), 1, t
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    return a.ctypes.data, 0, a
+
+
+def count_radial(a: Grid, ra, b: Grid | None, rb, aperture: float, edges, out=None, stream=None,
+                 with_stats: bool = False):
+    """cute_count_radial: pairs closer than ``aperture`` radians binned by the
+    difference of their redshifts ``ra`` / ``rb`` (one per object, in each
+    grid's input order; ``b is None``: autocorrelation). Returns uint64
+    counts (numpy), or fills ``out`` (a torch 64-bit device tensor)."""
+    lib = load()
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    pa, da, ka = _values(ra)
+    pb, db, kb = (pa, da, ka) if b is None else _values(rb)
+    if da != db:
+        raise ValueError("ra and rb must both be on the host or both on the device")
+    st = CountStats()
+    if out is None:
+        counts = np.zeros(len(e) - 1, dtype=np.uint64)
+        ptr, on_dev = counts.ctypes.data, 0
+    else:
+        counts, ptr, on_dev = out, out.data_ptr(), 1
+    _check(lib.cute_count_radial(a.handle, pa, None if b is None else b.handle, pb, da,
+                                 float(aperture), len(e) - 1,
+                                 e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptr, on_dev,
+                                 ctypes.byref(st), _stream_handle(stream)))
+    return (counts, st.as_dict()) if with_stats else counts
 
 
 def tune_grid(pos, geom: int, binning: Binning, box_size: float = 0.0, r_max: float = 0.0,

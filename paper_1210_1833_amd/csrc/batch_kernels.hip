@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256, 4) void k_count_batch(BatchArgs BA) {
             do_tile<MODE, PREC, EST, true, false>(P, W, S, B1, B2, T1, T2, lane, tl);
         }
         // the re-test queue refers to this item's points: empty it now
-        if (PREC == P_FP32E)
+        if constexpr (PREC == P_FP32E)
             W.tail = drain_queue<MODE, EST>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2,
                                             lane, W.tail, true);
         if (lane == 0) {

@@ -69,12 +69,24 @@ extern "C" const char* cute_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
+// A radial count: redshifts per point (input order of each grid), the
+// redshift-difference edges; the angular aperture is the reach of the THETA
+// binning passed beside it.
+struct RadialSpec {
+    const double* ra;
+    const double* rb;
+    int on_device;
+    int n;
+    const double* edges;
+    double aperture;
+};
+
 // One pair count; with max_tiles > 0 only an evenly spread sample of about
 // max_tiles home tiles is counted (the tuner's sample).
 cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binning* bins,
                        cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                        cute_count_stats* st, void* stream, uint32_t max_tiles,
-                       double* sampled_share = nullptr) {
+                       double* sampled_share = nullptr, const RadialSpec* rad = nullptr) {
     if (!ga) return fail(CUTE_E_INVALID_ARG, "grid a is NULL");
     if (!counts) return fail(CUTE_E_INVALID_ARG, "counts is NULL");
     cute_status s = validate_binning(bins);
@@ -96,6 +108,23 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     ItemGeom geo;
     if ((s = plan_item(A, B, is_auto, bins, pl, &geo)) != CUTE_OK) return s;
     plan_bands(bins, geo.em, pl);
+    if (rad) {
+        // the aperture binning gave the geometry; the histogram is over the
+        // redshift difference, compared with the unsquared edges
+        CountArgs& r = pl.a;
+        const double c = 2.0 * std::sin(0.5 * rad->aperture);
+        r.ap2 = c * c;
+        pl.mode = M_RADIAL;
+        pl.est = E_LIN;
+        pl.T1.assign(rad->edges, rad->edges + rad->n + 1);
+        pl.T2.assign(1, 0.0);
+        pl.band1.assign(rad->n, make_float2(0.f, 0.f));
+        pl.band2.assign(1, make_float2(0.f, 0.f));
+        r.n1 = rad->n;
+        r.n2 = 0;
+        r.nbins = rad->n;
+        r.n2p1 = 1;
+    }
     if ((s = plan_lds(pl, 0)) != CUTE_OK) return s;
     CountArgs a = pl.a;
     apply_item(geo, &a);
@@ -130,6 +159,20 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     CUTE_HIP(hipMemcpyAsync(blob, hb.data(), total, hipMemcpyHostToDevice, hs));
     unsigned long long* work = reinterpret_cast<unsigned long long*>(blob + oWK);
     CountArgs* dargs = reinterpret_cast<CountArgs*>(blob + oAR);
+    if (rad) {
+        // redshifts in each grid's sorted order
+        double *rsa = nullptr, *rsb = nullptr;
+        if ((s = tmp.alloc(&rsa, (size_t)A.n)) != CUTE_OK) return s;
+        if ((s = gather_values(A, rad->ra, rad->on_device != 0, rsa, hs)) != CUTE_OK) return s;
+        if (is_auto) {
+            rsb = rsa;
+        } else {
+            if ((s = tmp.alloc(&rsb, (size_t)B.n)) != CUTE_OK) return s;
+            if ((s = gather_values(B, rad->rb, rad->on_device != 0, rsb, hs)) != CUTE_OK) return s;
+        }
+        a.rA = rsa;
+        a.rB = rsb;
+    }
     const int4* dst = geo.stencil.empty() ? nullptr : reinterpret_cast<const int4*>(blob + oST);
     a.stencil = dst;
     a.nst = (int)geo.stencil.size();
@@ -230,6 +273,35 @@ extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb
                                         uint64_t* counts, int32_t counts_on_device,
                                         cute_count_stats* st, void* stream) {
     return count_impl(ga, gb, bins, prec, counts, counts_on_device, st, stream, 0);
+}
+
+extern "C" cute_status cute_count_radial(const cute_grid* a, const double* ra, const cute_grid* b,
+                                         const double* rb, int32_t r_on_device, double aperture,
+                                         int32_t n_bins, const double* edges, uint64_t* counts,
+                                         int32_t counts_on_device, cute_count_stats* st,
+                                         void* stream) {
+    if (!a) return fail(CUTE_E_INVALID_ARG, "grid a is NULL");
+    const bool is_auto = (b == nullptr || b == a);
+    if ((a->h.n > 0 && !ra) || (!is_auto && b->h.n > 0 && !rb))
+        return fail(CUTE_E_INVALID_ARG, "redshift pointer is NULL");
+    if (!(aperture > 0.0 && aperture <= 3.14159265358979323846))
+        return fail(CUTE_E_INVALID_ARG, "aperture must be in (0, pi]");
+    if (n_bins < 1 || n_bins > (1 << 20) || !edges)
+        return fail(CUTE_E_INVALID_ARG, "need n_bins >= 1 and n_bins + 1 edges");
+    for (int k = 0; k <= n_bins; k++)
+        if (!std::isfinite(edges[k]) || edges[k] < 0.0 || (k > 0 && !(edges[k - 1] < edges[k])))
+            return fail(CUTE_E_INVALID_ARG, "edges must be finite, >= 0 and strictly increasing");
+    if (a->h.wt != nullptr || (!is_auto && b->h.wt != nullptr))
+        return fail(CUTE_E_UNSUPPORTED, "radial counts take catalogs, not pixel maps");
+    const double ae[2] = {0.0, aperture};
+    cute_binning ab;
+    memset(&ab, 0, sizeof(ab));
+    ab.kind = CUTE_BIN_THETA;
+    ab.n1 = 1;
+    ab.edges1 = ae;
+    RadialSpec rs{ra, is_auto ? ra : rb, r_on_device, n_bins, edges, aperture};
+    return count_impl(a, b, &ab, CUTE_PREC_FP64, counts, counts_on_device, st, stream, 0, nullptr,
+                      &rs);
 }
 
 extern "C" cute_status cute_tune_grid(const double* x, const double* y, const double* z,

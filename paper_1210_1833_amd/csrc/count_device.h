@@ -20,6 +20,7 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 typedef const __attribute__((address_space(4))) float* cfp;
 typedef const __attribute__((address_space(4))) double* cdp;
 typedef const __attribute__((address_space(4))) uint32_t* cu32p;
+typedef const __attribute__((address_space(4))) double* cf64p;
 
 __device__ __forceinline__ float4 load_u32x4f(const float4* p, uint32_t j) {
     const cfp f = (cfp)(const void*)p;
@@ -616,11 +617,27 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     }
 }
 
+// Radial pairs (Sec. 2.1, radial 2PCF; Sec. 3.4): inside the aperture when
+// the chord^2 of the unit vectors is below ap2, then binned by the redshift
+// difference |r_i - r_j| against the unsquared edges T1 (half-open).
+__device__ __forceinline__ uint32_t classify_radial(const CountArgs& P, const double* T1, double d2,
+                                                    double dr) {
+    if (!(d2 < P.ap2)) return kNoBin;
+    const int n = P.n1;
+    if (!(T1[0] <= dr && dr < T1[n])) return kNoBin;
+    int lo = 0, hi = n;  // T1[lo] <= dr < T1[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (T1[mid] <= dr) lo = mid; else hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
 template <int MODE, int EST, bool PM, bool WT, bool MASKED, bool SHIFTED, uint32_t U>
 __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const double* T1,
                                        const double* T2, int lane, bool lvalid, bool lmask,
                                        uint32_t lj, double qx, double qy, double qz, double sx, double sy,
-                                       double sz, uint32_t lw, uint32_t h) {
+                                       double sz, uint32_t lw, uint32_t h, double qr) {
     double hx[U], hy[U], hz[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -633,6 +650,12 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     home_valid<PM, U>(P, h, hv);
     uint32_t hw[U];
     home_weights<WT, U>(P, h, hw);
+    double hr[U];
+    if constexpr (MODE == M_RADIAL) {
+        const cf64p ra = (cf64p)(const void*)P.rA;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) hr[u] = ra[h + u];
+    }
     uint32_t bin[U];
     bool cnt[U];
 #pragma unroll
@@ -655,6 +678,11 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
         }
         int k1 = 0, k2 = 0;
         const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if constexpr (MODE == M_RADIAL) {
+            bin[u] = classify_radial(P, T1, d2, fabs(hr[u] - qr));
+            cnt[u] = act & (bin[u] != kNoBin);
+            continue;
+        }
         const float v = (float)d2;
         if (MODE == M_MONO || MODE == M_THETA) {
             k1 = guess1<MODE, EST>(P, v);
@@ -701,8 +729,9 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     // a neighbour excluded by the point mask leaves its lane idle
     if (PM && P.mbB != nullptr && lvalid) lvalid = ((P.mbB[C.lj >> 5] >> (C.lj & 31u)) & 1u) == 0u;
     const uint32_t lw = lvalid ? (WT ? P.wB[C.lj] : pair_weight(P, C.lj)) : 1u;
-    if (PREC == P_FP64) {
-        double qx = 0.0, qy = 0.0, qz = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    if constexpr (PREC == P_FP64) {
+        double qx = 0.0, qy = 0.0, qz = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, qr = 0.0;
+        if (MODE == M_RADIAL && lvalid) qr = P.rB[C.lj];
         if (lvalid) {
             const P64 q = P.B.p64[C.lj];
             qx = q.x;
@@ -717,10 +746,10 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         uint32_t h = ts;                                                                        \
         for (; h + U <= te; h += U)                                                             \
             step64<MODE, EST, PM, WT, MSK, SH, U>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
-                                          sx, sy, sz, lw, h);                                   \
+                                          sx, sy, sz, lw, h, qr);                               \
         for (; h < te; h++)                                                                     \
             step64<MODE, EST, PM, WT, MSK, SH, 1>(P, W, T1, T2, lane, lvalid, C.lmask, C.lj, qx, qy, qz, \
-                                          sx, sy, sz, lw, h);                                   \
+                                          sx, sy, sz, lw, h, qr);                               \
     }
         if (C.masked) {
             if (C.shifted) CUTE_RUN64(true, true) else CUTE_RUN64(true, false)

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
         tl.c0c1 = uni(tp[4 * t + 3]);
         do_tile<MODE, PREC, EST, false, WT>(P, W, S, B1, B2, T1, T2, lane, tl);
     }
-    if (PREC == P_FP32E)
+    if constexpr (PREC == P_FP32E)
         W.tail = drain_queue<MODE, EST>(P.self, W.hist, W.qi, W.qj, W.qc, W.rstat, B1, B2, T1, T2, lane,
                                         W.tail, true);
     if (lane == 0) {
@@ -175,6 +175,11 @@ cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int
         case M_RMU_MID: return launch_prec<M_RMU_MID>(args, prec, est, wg_waves, lds_bytes, stream, grid_used);
         case M_SIGMAPI: return launch_prec<M_SIGMAPI>(args, prec, est, wg_waves, lds_bytes, stream, grid_used);
         case M_THETA: return launch_prec<M_THETA>(args, prec, est, wg_waves, lds_bytes, stream, grid_used);
+        case M_RADIAL:
+            // few pairs fall inside an aperture: FP64 only
+            if (prec != P_FP64 || args.wA != nullptr)
+                return fail(CUTE_E_UNSUPPORTED, "radial counts are FP64 and unweighted");
+            return launch_one<M_RADIAL, P_FP64, E_LIN, false>(args, wg_waves, lds_bytes, stream, grid_used);
         default: return fail(CUTE_E_INTERNAL, "unknown mode");
     }
 }

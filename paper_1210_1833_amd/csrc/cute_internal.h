@@ -24,7 +24,7 @@ constexpr int kSpanCap = 192;     // neighbour spans buffered per wave
 constexpr int kWgWaves = 4;       // waves per count workgroup
 
 // Kinds of pair classification the kernels are specialised for.
-enum Mode : int { M_MONO = 0, M_RMU_Z = 1, M_RMU_MID = 2, M_SIGMAPI = 3, M_THETA = 4 };
+enum Mode : int { M_MONO = 0, M_RMU_Z = 1, M_RMU_MID = 2, M_SIGMAPI = 3, M_THETA = 4, M_RADIAL = 5 };
 // How a bin index is estimated from the squared separation.
 enum Est : int { E_LIN = 0, E_LOG = 1 };
 // Precision path.
@@ -124,6 +124,11 @@ struct CountArgs {
     // wA[i] * wB[j]; nullptr for unweighted catalogs
     const uint32_t* wA;
     const uint32_t* wB;
+    // radial pairs (M_RADIAL): redshifts in sorted order and the chord^2 of
+    // the aperture; T1 then holds the unsquared redshift-difference edges
+    const double* rA;
+    const double* rB;
+    double ap2;
 };
 
 // A batched launch: the items (one CountArgs each, in device memory) share
@@ -232,6 +237,11 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
                         hipStream_t s);
 
 // persistent count launch; *grid_used receives the number of workgroups
+// out[i] = in[input index of sorted point i] for the n points of g (in:
+// host or device memory); waits for the stream; rejects non-finite values.
+cute_status gather_values(const GridHost& g, const double* in, bool on_device, double* out,
+                          hipStream_t s);
+
 // Add the pairs of objects that share a pixel of a pixel map to *bin.
 cute_status add_pixel_self_pairs(const GridHost& g, unsigned long long* bin, hipStream_t s);
 

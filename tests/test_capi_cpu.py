@@ -192,3 +192,12 @@ def test_pixel_map_rejects_bad_arguments(lib):
     assert lib.cute_build_pixel_map(*X, 4, 16, 32, None, None, ctypes.byref(h)) == cute.E_INVALID_ARG
     assert lib.cute_build_pixel_map(*X, 4, 16, 32, ctypes.byref(ps), None, None) == cute.E_INVALID_ARG
     assert lib.cute_pixel_map_read(None, None, None, None) == cute.E_INVALID_ARG
+
+
+def test_radial_rejects_bad_arguments(lib):
+    e = np.linspace(0.0, 0.1, 5)
+    z = np.zeros(4)
+    out = np.zeros(4, dtype=np.uint64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.cute_count_radial(None, z.ctypes.data, None, None, 0, 0.01, 4, e.ctypes.data_as(dp),
+                                 out.ctypes.data, 0, None, None) == cute.E_INVALID_ARG

@@ -103,7 +103,10 @@ typedef struct {
                           0 = chosen by the library                           */
     int32_t device_ptrs; /* nonzero: x, y, z are device pointers             */
     int32_t tile_points; /* most points in one home tile when this grid is the
-                            first argument of a count, 1..64; 0 = 64         */
+                            first argument of a count, 1..64; 0 = 64, halved
+                            (down to 16) by cute_count_pairs and
+                            cute_count_radial while the count has fewer tiles
+                            than two per wave slot of the GPU              */
 } cute_grid_params;
 
 typedef struct {

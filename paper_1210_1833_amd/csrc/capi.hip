@@ -187,7 +187,22 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     Tile* tiles = nullptr;
     uint32_t ntiles = 0;
     if (A.n > 0 && B.n > 0) {
-        if ((s = build_tiles(A, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
+        GridHost At = A;
+        if ((s = build_tiles(At, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
+        // Too few tiles to give every wave slot of the chip two: cut them
+        // shorter (default tile size only; not below 16 points, where the
+        // per-tile neighbour walk starts to dominate).
+        int ncu = 0;
+        if (A.tile_auto && max_tiles == 0 &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+            const uint32_t want = (uint32_t)ncu * 16u * 2u;
+            while (ntiles < want && At.tile_max > 16) {
+                At.tile_max = std::max(16, At.tile_max / 2);
+                dfree(tiles, hs);
+                tiles = nullptr;
+                if ((s = build_tiles(At, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
+            }
+        }
     }
     if ((s = order_tiles(A, B, dst, a.nst, is_auto, geo.periodic != 0, &tiles, ntiles, hs)) !=
         CUTE_OK) {

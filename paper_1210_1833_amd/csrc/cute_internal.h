@@ -162,6 +162,7 @@ struct GridHost {
     uint32_t* cstart;
     void* block;         // the one device allocation holding p64, p32 and cstart
     int tile_max;        // most points in a home tile (1..64)
+    bool tile_auto;      // tile_max is the default (counts may cut tiles shorter)
     // pixel maps: occupancy of each point in sorted order, and the non-empty
     // pixels (ids ascending) with their occupancies, all in one allocation
     uint32_t* wt;        // nullptr for plain catalogs

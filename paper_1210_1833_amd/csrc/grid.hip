@@ -382,6 +382,7 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
     g.geom = p->geom;
     g.n = n;
     g.tile_max = p->tile_points > 0 ? p->tile_points : 64;
+    g.tile_auto = p->tile_points == 0;
 
     EventTimer timer(s);
     TempList tmp(s);

@@ -1,0 +1,98 @@
+"""GPU parity at the size limits of one count: the largest histograms that
+fit in one workgroup's 160 KB of LDS (one copy, one workgroup per CU), and
+the first sizes that do not (a clean CUTE_E_UNSUPPORTED), one-point home
+tiles, and the limit of 64 points per tile, all against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import catalogs
+import oracle
+import paper_1210_1833_amd as cute
+
+pytestmark = pytest.mark.gpu
+
+EXACT = [cute.PREC_FP64, cute.PREC_FP32_EDGE]
+
+# LDS bytes of one count workgroup: the tables (FP64 thresholds and FP32
+# bands of both dimensions), four waves' re-test queues, statistics and span
+# buffers, and the 64-bit histogram; 160 KB is the per-workgroup maximum.
+LDS_MAX = 160 * 1024
+PER_WAVE = 12 * 128 + 16 + 12 * 192
+
+
+def lds_bytes(n1, n2):
+    tables = 8 * (n1 + 1) + 8 * (n2 + 1) + 8 * n1 + 8 * max(n2, 1)
+    return tables + 4 * PER_WAVE + 8 * n1 * max(n2, 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    cute.load()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_lds_model_brackets_the_limits():
+    assert lds_bytes(6183, 0) <= LDS_MAX < lds_bytes(6184, 0)
+    assert lds_bytes(134, 134) <= LDS_MAX < lds_bytes(135, 135)
+
+
+@pytest.mark.parametrize("n", [6183])
+def test_largest_monopole_histogram(n):
+    a = catalogs.mixed_periodic(4000, 200.0, seed=201)
+    e = np.linspace(0.0, 60.0, n + 1)
+    bn = cute.Binning(cute.BIN_MONO, e)
+    want = oracle.count_pairs(a, None, oracle.Binning(oracle.MONO, e))
+    g = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=60.0)
+    for prec in EXACT:
+        say("MONO %d bins, prec %d" % (n, prec))
+        np.testing.assert_array_equal(cute.count_pairs(g, None, bn, prec), want)
+    with pytest.raises(cute.CuteError) as ex:
+        cute.count_pairs(g, None, cute.Binning(cute.BIN_MONO, np.linspace(0.0, 60.0, n + 2)))
+    assert ex.value.status == cute.E_UNSUPPORTED
+
+
+def test_largest_rmu_histogram():
+    a = catalogs.mixed_periodic(4000, 200.0, seed=202)
+    b = catalogs.uniform_box(3000, 200.0, seed=203)
+    e1, e2 = np.linspace(0.0, 50.0, 135), np.linspace(0.0, 1.0, 135)
+    bn = cute.Binning(cute.BIN_RMU, e1, e2, los=cute.LOS_Z)
+    ob = oracle.Binning(oracle.RMU, e1, e2, los=oracle.LOS_Z)
+    ga = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=50.0)
+    gb = cute.build_grid(b, cute.GEOM_BOX_OPEN, r_max=50.0)
+    want_aa = oracle.count_pairs(a, None, ob).reshape(bn.shape)
+    want_ab = oracle.count_pairs(a, b, ob).reshape(bn.shape)
+    for prec in EXACT:
+        say("RMU 134 x 134 bins, prec %d" % prec)
+        np.testing.assert_array_equal(cute.count_pairs(ga, None, bn, prec), want_aa)
+        np.testing.assert_array_equal(cute.count_pairs(ga, gb, bn, prec), want_ab)
+    big = cute.Binning(cute.BIN_RMU, np.linspace(0.0, 50.0, 136), np.linspace(0.0, 1.0, 136),
+                       los=cute.LOS_Z)
+    with pytest.raises(cute.CuteError) as ex:
+        cute.count_pairs(ga, None, big)
+    assert ex.value.status == cute.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("tile", [1, 3, 64])
+def test_tile_sizes(tile):
+    """One-point tiles, a ragged odd size and the 64-point maximum give the
+    same counts as the oracle, periodic and open."""
+    a = catalogs.mixed_periodic(5000, 300.0, seed=204)
+    e = np.linspace(0.0, 40.0, 21)
+    for geom, L in ((cute.GEOM_BOX_PERIODIC, 300.0), (cute.GEOM_BOX_OPEN, 0.0)):
+        ob = oracle.Binning(oracle.MONO, e, periodic=L > 0, L=L)
+        want = oracle.count_pairs(a, None, ob, prune=True)
+        g = cute.build_grid(a, geom, box_size=L, r_max=40.0, tile_points=tile)
+        for prec in EXACT:
+            say("tile %d geom %d prec %d" % (tile, geom, prec))
+            np.testing.assert_array_equal(cute.count_pairs(g, None, cute.Binning(cute.BIN_MONO, e),
+                                                           prec), want)

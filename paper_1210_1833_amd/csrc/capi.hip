@@ -114,6 +114,7 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
         CountArgs& r = pl.a;
         const double c = 2.0 * std::sin(0.5 * rad->aperture);
         r.ap2 = c * c;
+        r.top64 = r.ap2;
         pl.mode = M_RADIAL;
         pl.est = E_LIN;
         pl.T1.assign(rad->edges, rad->edges + rad->n + 1);

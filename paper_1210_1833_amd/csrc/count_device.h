@@ -533,6 +533,16 @@ __device__ __forceinline__ void home_valid(const CountArgs& P, uint32_t h, bool*
     }
 }
 
+// Modes whose pairs are all out when the separation is past the top edge
+// (r, or the chord of theta, or the aperture of radial pairs): a step whose
+// every pair lies there is skipped after the separations alone. Points are
+// sorted by cell and home tiles are compact, so on clustered catalogs whole
+// steps (four home points against a chunk of nearby neighbours) often fall
+// beyond r_max together; the separations are still formed for every pair.
+template <int MODE>
+constexpr bool kTopSkip = MODE == M_MONO || MODE == M_RMU_Z || MODE == M_RMU_MID ||
+                          MODE == M_THETA || MODE == M_RADIAL;
+
 // Weights of home points h .. h+U-1 (wave-uniform, scalar loads).
 template <bool WT, uint32_t U>
 __device__ __forceinline__ void home_weights(const CountArgs& P, uint32_t h, uint32_t* hw) {
@@ -564,6 +574,18 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     home_valid<PM, U>(P, h, hv);
     uint32_t hw[U];
     home_weights<WT, U>(P, h, hw);
+    if constexpr (kTopSkip<MODE>) {
+        // every pair of the step on the clean-out side of the top edge:
+        // nothing to count or re-test (see kTopSkip)
+        float vmin = 0.f;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            const float dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
+            const float v = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            vmin = u == 0 ? v : fminf(vmin, v);
+        }
+        if (__builtin_amdgcn_ballot_w64(vmin < P.out_hi) == 0ull) return;
+    }
     uint32_t off[U];
     bool cnt[U], amb[U];
 #pragma unroll
@@ -650,6 +672,22 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     home_valid<PM, U>(P, h, hv);
     uint32_t hw[U];
     home_weights<WT, U>(P, h, hw);
+    if constexpr (kTopSkip<MODE>) {
+        // every pair of the step at or past the top threshold (exact FP64)
+        double dmin = 0.0;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            double dx = hx[u] - qx, dy = hy[u] - qy, dz = hz[u] - qz;
+            if (SHIFTED) {
+                dx = dx - sx;
+                dy = dy - sy;
+                dz = dz - sz;
+            }
+            const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            dmin = u == 0 ? d2 : fmin(dmin, d2);
+        }
+        if (__builtin_amdgcn_ballot_w64(dmin < P.top64) == 0ull) return;
+    }
     double hr[U];
     if constexpr (MODE == M_RADIAL) {
         const cf64p ra = (cf64p)(const void*)P.rA;

@@ -129,6 +129,9 @@ struct CountArgs {
     const double* rA;
     const double* rB;
     double ap2;
+    // the FP64 top threshold: a pair with d2 >= top64 is never counted
+    // (T1[n1] for MONO, RMU and THETA; ap2 for radial pairs)
+    double top64;
 };
 
 // A batched launch: the items (one CountArgs each, in device memory) share

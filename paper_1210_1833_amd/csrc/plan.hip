@@ -173,6 +173,7 @@ void plan_binning(const cute_binning* b, Plan& pl) {
     }
     a.bot32 = (float)pl.T1[0];
     a.top32 = (float)pl.T1[n1];
+    a.top64 = pl.T1[n1];
     // biased FP32 estimates: fma(t + s, a, 2^23) rounds to 2^23 + floor(t a + b)
     // when s = (b - 1/2) / a; the clamps are the bits of 2^23 + n - 1
     a.n2p1 = n2 > 0 ? n2 : 1;

@@ -533,15 +533,17 @@ __device__ __forceinline__ void home_valid(const CountArgs& P, uint32_t h, bool*
     }
 }
 
-// Modes whose pairs are all out when the separation is past the top edge
-// (r, or the chord of theta, or the aperture of radial pairs): a step whose
-// every pair lies there is skipped after the separations alone. Points are
-// sorted by cell and home tiles are compact, so on clustered catalogs whole
-// steps (four home points against a chunk of nearby neighbours) often fall
-// beyond r_max together; the separations are still formed for every pair.
+// Every mode has a separation past which no pair is counted: the top edge of
+// r or of the chord of theta, the aperture of radial pairs, and for sigma-pi
+// sqrt(sigma_max^2 + pi_max^2), since sigma^2 + pi^2 = r^2 for any line of
+// sight. A step whose every pair lies past it (skip32 in FP32, on the
+// clean-out side of the rounding band; top64 in FP64) is skipped after the
+// separations alone. Points are sorted by cell and home tiles are compact, so
+// on clustered catalogs whole steps (four home points against a chunk of
+// nearby neighbours) often fall beyond r_max together; the separations are
+// still formed for every pair.
 template <int MODE>
-constexpr bool kTopSkip = MODE == M_MONO || MODE == M_RMU_Z || MODE == M_RMU_MID ||
-                          MODE == M_THETA || MODE == M_RADIAL;
+constexpr bool kTopSkip = true;
 
 // Weights of home points h .. h+U-1 (wave-uniform, scalar loads).
 template <bool WT, uint32_t U>
@@ -584,7 +586,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
             const float v = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
             vmin = u == 0 ? v : fminf(vmin, v);
         }
-        if (__builtin_amdgcn_ballot_w64(vmin < P.out_hi) == 0ull) return;
+        if (__builtin_amdgcn_ballot_w64(vmin < P.skip32) == 0ull) return;
     }
     uint32_t off[U];
     bool cnt[U], amb[U];

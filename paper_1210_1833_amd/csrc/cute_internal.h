@@ -130,8 +130,12 @@ struct CountArgs {
     const double* rB;
     double ap2;
     // the FP64 top threshold: a pair with d2 >= top64 is never counted
-    // (T1[n1] for MONO, RMU and THETA; ap2 for radial pairs)
+    // (T1[n1] for MONO, RMU and THETA; ap2 for radial pairs; for SIGMAPI
+    // (sigma_max^2 + pi_max^2)(1 + 1e-12), rounded up)
     double top64;
+    // the FP32 counterpart: d2_32 >= skip32 implies d2 >= top64 for the
+    // canonical value (out_hi, or its SIGMAPI analogue)
+    float skip32;
 };
 
 // A batched launch: the items (one CountArgs each, in device memory) share

@@ -174,6 +174,13 @@ void plan_binning(const cute_binning* b, Plan& pl) {
     a.bot32 = (float)pl.T1[0];
     a.top32 = (float)pl.T1[n1];
     a.top64 = pl.T1[n1];
+    if (b->kind == CUTE_BIN_SIGMAPI) {
+        // sigma^2 + pi^2 = r^2 exactly for the FP64 differences and any line
+        // of sight; the canonical products err by a few ulp of r^2 |l|^2, far
+        // inside a 1e-12 relative margin
+        const double r2 = b->edges1[n1] * b->edges1[n1] + b->edges2[n2] * b->edges2[n2];
+        a.top64 = std::nextafter(r2 * (1.0 + 1e-12), INFINITY);
+    }
     // biased FP32 estimates: fma(t + s, a, 2^23) rounds to 2^23 + floor(t a + b)
     // when s = (b - 1/2) / a; the clamps are the bits of 2^23 + n - 1
     a.n2p1 = n2 > 0 ? n2 : 1;
@@ -361,6 +368,10 @@ void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
         }
         a.out_hi = -(float)pl.T1[n1];
         a.out_lo = pl.T1[0] == 0.0 ? kBig : -(float)pl.T1[0];
+        // FP32 skip: d2_32 past top64 plus the FP32 and FP64 error of d2 at
+        // that separation
+        const double rt = std::sqrt(a.top64);
+        a.skip32 = up32(a.top64 + 1.5 * d2_bound(rt * (1.0 + 1e-6) + 2.0 * ec, ec, ec64));
     } else {
         std::vector<float> lo_e(n1 + 1), hi_e(n1 + 1);
         for (int k = 0; k <= n1; k++) {
@@ -374,6 +385,7 @@ void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
         for (int k = 0; k < n1; k++) pl.band1[k] = make_float2(lo_e[k], hi_e[k + 1]);
         a.out_hi = lo_e[n1];
         a.out_lo = hi_e[0];
+        a.skip32 = a.out_hi;
     }
     if (pl.mode == M_RMU_Z) {
         // |F - exact| <= 2 sqrt(2) ec r + 3 ec^2 + 8.1 u S, plus the FP64 terms;

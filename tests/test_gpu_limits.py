@@ -1,7 +1,9 @@
-"""GPU parity at the size limits of one count: the largest histograms that
-fit in one workgroup's 160 KB of LDS (one copy, one workgroup per CU), and
-the first sizes that do not (a clean CUTE_E_UNSUPPORTED), one-point home
-tiles, and the limit of 64 points per tile, all against the oracle."""
+"""GPU parity at the limits of one count: the largest histograms that fit
+in one workgroup's 160 KB of LDS (one copy, one workgroup per CU), and the
+first sizes that do not (a clean CUTE_E_UNSUPPORTED), one-point home tiles,
+the limit of 64 points per tile, and catalogs whose steps mostly lie past
+the top edge with a few pairs right at it (the step skip), all against the
+oracle."""
 import sys
 
 import numpy as np
@@ -96,3 +98,49 @@ def test_tile_sizes(tile):
             say("tile %d geom %d prec %d" % (tile, geom, prec))
             np.testing.assert_array_equal(cute.count_pairs(g, None, cute.Binning(cute.BIN_MONO, e),
                                                            prec), want)
+
+
+def _shell_catalog(rmax, seed, n_blobs=300, per=40, spread=0.5):
+    """Blobs whose centres sit at separations close to rmax from other blobs
+    (just inside, exactly at, just outside), so that most steps of a count lie
+    past the top edge and a few hold single pairs at the edge."""
+    rng = np.random.default_rng(seed)
+    centres = [np.zeros(3)]
+    for k in range(n_blobs - 1):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        f = rng.choice([1.0 - 1e-3, 1.0 - 1e-7, 1.0, 1.0 + 1e-7, 1.0 + 1e-3, 1.5, 2.0])
+        centres.append(centres[rng.integers(0, len(centres))] + d * rmax * f)
+    c = np.array(centres)
+    pts = np.repeat(c, per, axis=0) + rng.normal(scale=spread, size=(len(c) * per, 3))
+    pts[::per] = c  # blob centres themselves, so some pairs sit right at the edge
+    return pts + 1000.0
+
+
+@pytest.mark.parametrize("kind", ["mono", "rmu", "sigmapi"])
+def test_top_edge_skip_is_exact(kind):
+    """Counts where most steps lie past r_max and a few pairs sit at it
+    (blob centres at r_max (1 - 1e-7), r_max, r_max (1 + 1e-7)): FP64 and
+    FP32_EDGE equal the oracle."""
+    rmax = 40.0
+    a = _shell_catalog(rmax, 301)
+    b = _shell_catalog(rmax, 302)
+    if kind == "mono":
+        e1, e2, ck, ok, los, olos = np.linspace(0.0, rmax, 9), None, cute.BIN_MONO, oracle.MONO, cute.LOS_Z, oracle.LOS_Z
+    elif kind == "rmu":
+        e1, e2, ck, ok, los, olos = np.linspace(0.0, rmax, 9), np.linspace(0.0, 1.0, 6), cute.BIN_RMU, oracle.RMU, cute.LOS_Z, oracle.LOS_Z
+    else:
+        s = rmax / np.sqrt(2.0)
+        e1, e2, ck, ok, los, olos = np.linspace(0.0, s, 9), np.linspace(0.0, s, 9), cute.BIN_SIGMAPI, oracle.SIGMAPI, cute.LOS_MIDPOINT, oracle.LOS_MID
+    bn = cute.Binning(ck, e1, e2, los=los)
+    ob = oracle.Binning(ok, e1, e2, los=olos)
+    reach = oracle.rmax(ob)
+    ga = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=reach)
+    gb = cute.build_grid(b, cute.GEOM_BOX_OPEN, r_max=reach)
+    want_aa = oracle.count_pairs(a, None, ob, prune=True).reshape(bn.shape)
+    want_ab = oracle.count_pairs(a, b, ob, prune=True).reshape(bn.shape)
+    assert want_aa.sum() > 0 and want_ab.sum() > 0
+    for prec in EXACT:
+        say("top-edge skip, %s, prec %d" % (kind, prec))
+        np.testing.assert_array_equal(cute.count_pairs(ga, None, bn, prec), want_aa)
+        np.testing.assert_array_equal(cute.count_pairs(ga, gb, bn, prec), want_ab)

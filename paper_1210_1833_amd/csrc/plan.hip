@@ -325,6 +325,16 @@ cute_status plan_item(const GridHost& A, const GridHost& B, bool is_auto, const 
                 const int left = (int)std::ceil(wc), right = (int)std::floor(wc) + 1;
                 g->stencil.push_back(make_int4(dy, dz, left, right));
             }
+        // nearest rows first: a chunk that spans the end of one row and the
+        // start of the next then holds neighbours at similar distances, so
+        // that whole steps past the top edge are more common
+        auto gap2 = [&](const int4& e) {
+            const double gy = std::max(0, std::abs(e.x) - 1) * A.ay;
+            const double gz = std::max(0, std::abs(e.y) - 1) * A.az;
+            return gy * gy + gz * gz;
+        };
+        std::stable_sort(g->stencil.begin(), g->stencil.end(),
+                         [&](const int4& u, const int4& v) { return gap2(u) < gap2(v); });
         if (g->stencil.size() > 65536) g->stencil.clear();
     }
 

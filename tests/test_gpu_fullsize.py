@@ -149,3 +149,50 @@ def test_batched_mocks_and_jackknife_full_size():
     for q, r in enumerate(regs):
         rest, reg, cross = got[len(gm) + 3 * q: len(gm) + 3 * q + 3]
         np.testing.assert_array_equal(rest + reg + cross, dd_base, err_msg="region %d" % r)
+
+
+def test_rmu_dr_rr_full_size_and_estimators():
+    """The r-mu workload at its full size beyond DD: 1e6 clustered data and
+    2e6 uniform randoms. The DR and RR rows of 64 seeded sample points equal
+    the oracle's; the full DR and RR in FP32_EDGE equal FP64; Landy-Szalay
+    xi(r, mu) and its multipoles from the full counts agree with the oracle's
+    exact-rational estimators to 1e-12."""
+    import json
+    import os
+
+    from oracle import estimators as est
+    d, r = catalogs.config2()
+    e1, e2 = np.arange(41) * 5.0, np.arange(51) / 50.0
+    bn = cute.Binning(cute.BIN_RMU, e1, e2, los=cute.LOS_Z)
+    ob = oracle.Binning(oracle.RMU, e1, e2, los=oracle.LOS_Z)
+    gd = dgrid(d, cute.GEOM_BOX_OPEN, 200.0)
+    gr = dgrid(r, cute.GEOM_BOX_OPEN, 200.0)
+    for cat, name in ((d, "D"), (r, "R")):
+        s = sample(cat, 64, seed=51 if name == "D" else 52)
+        gs = cute.build_grid(s, cute.GEOM_BOX_OPEN, r_max=200.0)
+        want = oracle.count_pairs(s, r, ob, prune=True).reshape(bn.shape)
+        for prec in EXACT:
+            say("r-mu full size: %s-sample x R, prec %d" % (name, prec))
+            np.testing.assert_array_equal(cute.count_pairs(gs, gr, bn, prec), want)
+    say("r-mu full size: DR and RR, FP32_EDGE vs FP64")
+    dr = cute.count_pairs(gd, gr, bn, cute.PREC_FP32_EDGE)
+    np.testing.assert_array_equal(dr, cute.count_pairs(gd, gr, bn, cute.PREC_FP64))
+    rr = cute.count_pairs(gr, None, bn, cute.PREC_FP32_EDGE)
+    np.testing.assert_array_equal(rr, cute.count_pairs(gr, None, bn, cute.PREC_FP64))
+    golden = os.path.join(os.path.dirname(__file__), "golden", "c2_dd_rmu.json")
+    with open(golden) as f:
+        dd = np.array(json.load(f)["counts"], dtype=np.uint64).reshape(bn.shape)
+    nd, nr = len(d), len(r)
+    say("r-mu full size: Landy-Szalay and multipoles")
+    xi = cute.xi_estimate(cute.EST_LS, dd, dr, rr, nd, nr, bn)
+    want = est.landy_szalay(dd, dr, rr, nd, nr)
+    ok = ~np.isnan(want)
+    assert ok.all() and np.array_equal(np.isnan(xi), np.isnan(want))
+    rel = np.abs(xi[ok] - want[ok]) / np.maximum(np.abs(want[ok]), 1e-300)
+    assert rel.max() <= 1e-12, rel.max()
+    ells = (0, 2, 4)
+    got_m = cute.xi_multipoles(xi, bn, ells)
+    want_m = est.multipoles(want, e2, list(ells))
+    for a, ell in enumerate(ells):
+        scale = np.abs(want) @ est.multipole_weights_abs(e2, ell)
+        assert np.all(np.abs(got_m[a] - want_m[a]) <= 1e-12 * scale + 1e-300)

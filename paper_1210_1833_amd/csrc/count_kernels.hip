@@ -198,39 +198,50 @@ __device__ uint32_t walk_row_tiles(const uint32_t* __restrict__ cstart, const ui
     uint16_t cur_rg = 0;
     Tile cur{0u, 0u, 0u, 0u};
     bool open = false;
-    for (int c = 0; c < nx; c++) {
-        uint32_t pos = cs[c];
-        const uint32_t end = cs[c + 1];
-        while (pos < end) {
-            // the next run of points of one region inside this cell
-            uint32_t run = end - pos;
-            uint16_t rg = 0;
-            if (reg != nullptr) {
-                rg = reg[pos];
-                run = 1;
-                while (pos + run < end && reg[pos + run] == rg) run++;
-            }
-            while (run > 0) {
-                if (!open || fill == tmax || c - first + 1 > max_w || rg != cur_rg) {
-                    if (open) {
-                        if (out) out[o] = cur;
-                        o++;
-                    }
-                    open = true;
-                    fill = 0;
-                    first = c;
-                    cur_rg = rg;
-                    cur.start = pos;
-                    cur.end = pos;
-                    cur.row = (uint32_t)r;
-                    cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
+    // cell offsets in batches of eight (independent loads in flight); the
+    // batch loop is unrolled so that the offsets stay in registers
+    constexpr int kB = 8;
+    for (int cb = 0; cb < nx; cb += kB) {
+        uint32_t ofs[kB + 1];
+#pragma unroll
+        for (int i = 0; i <= kB; i++) ofs[i] = cb + i <= nx ? cs[cb + i] : 0u;
+#pragma unroll
+        for (int k = 0; k < kB; k++) {
+            const int c = cb + k;
+            if (c >= nx) break;
+            uint32_t pos = ofs[k];
+            const uint32_t end = ofs[k + 1];
+            while (pos < end) {
+                // the next run of points of one region inside this cell
+                uint32_t run = end - pos;
+                uint16_t rg = 0;
+                if (reg != nullptr) {
+                    rg = reg[pos];
+                    run = 1;
+                    while (pos + run < end && reg[pos + run] == rg) run++;
                 }
-                const uint32_t take = tmax - fill < run ? tmax - fill : run;
-                fill += take;
-                run -= take;
-                pos += take;
-                cur.end = pos;
-                cur.c0c1 = (cur.c0c1 & 0xffffu) | ((uint32_t)c << 16);
+                while (run > 0) {
+                    if (!open || fill == tmax || c - first + 1 > max_w || rg != cur_rg) {
+                        if (open) {
+                            if (out) out[o] = cur;
+                            o++;
+                        }
+                        open = true;
+                        fill = 0;
+                        first = c;
+                        cur_rg = rg;
+                        cur.start = pos;
+                        cur.end = pos;
+                        cur.row = (uint32_t)r;
+                        cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
+                    }
+                    const uint32_t take = tmax - fill < run ? tmax - fill : run;
+                    fill += take;
+                    run -= take;
+                    pos += take;
+                    cur.end = pos;
+                    cur.c0c1 = (cur.c0c1 & 0xffffu) | ((uint32_t)c << 16);
+                }
             }
         }
     }

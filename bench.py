@@ -67,7 +67,7 @@ def batched_leg(cute, torch, dev, runs=1):
     712 autocorrelations, one batch (two persistent launches in one graph)."""
     import catalogs
     t0 = time.perf_counter()
-    mocks, base, region = catalogs.config5()
+    mocks, base, region = catalogs.batched_mocks_256()
     L = 1000.0
     t_gen = time.perf_counter() - t0
     mono = cute.Binning(cute.BIN_MONO, np.arange(31) * 5.0)
@@ -294,7 +294,7 @@ def committed_traffic():
     """HBM bytes per count launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; None otherwise."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_count_rmu_c2_dd.json")
+    path = os.path.join(ROOT, "profiles", "k_count_rmu_clustered_1e6_dd.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -340,7 +340,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
-    d, _ = catalogs.config2()
+    d, _ = catalogs.clustered_box_1e6()
     n = len(d)
     xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (d.x, d.y, d.z)]
     bn = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(51) / 50.0, los=cute.LOS_Z)
@@ -380,7 +380,7 @@ def main():
     c64 = counts.cpu().numpy().astype(np.uint64)
 
     exact = bool(np.array_equal(c32, c64))
-    golden = os.path.join(ROOT, "tests", "golden", "c2_dd_rmu.json")
+    golden = os.path.join(ROOT, "tests", "golden", "clustered_1e6_dd_rmu.json")
     oracle_checked = False
     if os.path.exists(golden):
         with open(golden) as f:

@@ -12,8 +12,10 @@ sizes and kind of clustering.
 Every generator takes explicit sizes so that the tests can draw small versions
 of the same shapes. Random numbers come from numpy's ``Generator(PCG64(seed))``;
 each catalog is shuffled so that input order carries no spatial structure.
-Seeds follow ``1000 * config + role`` (role 1 data, 2 randoms, 3 blob centres,
-100+k mock k, 500 jackknife base).
+Seeds follow ``1000 * w + role``, with w numbering the workload (1 periodic
+uniform box, 2 clustered open box, 3 sigma-pi light cone, 4 angular cap,
+5 batched mocks, 6 the Table 2 light-cone subset) and role 1 data, 2 randoms,
+3 blob centres, 100+k mock k, 500 jackknife base.
 """
 from __future__ import annotations
 
@@ -25,7 +27,8 @@ import numpy as np
 __all__ = [
     "Catalog", "rng", "uniform_box", "gaussian_blobs", "sky_cap_lightcone",
     "comoving_distance_table", "cap_uniform", "cap_blobs", "mock_sizes",
-    "mixed_periodic", "config1", "config2", "config3", "config4", "config5",
+    "mixed_periodic", "periodic_uniform_2e4", "clustered_box_1e6", "lightcone_3e6",
+    "angular_cap_1e7", "batched_mocks_256", "lightcone_box", "table2", "unit_vectors",
     "sha256_of",
 ]
 
@@ -253,12 +256,12 @@ def mixed_periodic(n: int, box: float, seed: int, blob_frac: float = 0.5,
 # ----------------------------------------------------------------------------
 # The five workload shapes (scale factors give the small test versions)
 # ----------------------------------------------------------------------------
-def config1(n: int = 20_000, box: float = 1000.0) -> Catalog:
+def periodic_uniform_2e4(n: int = 20_000, box: float = 1000.0) -> Catalog:
     """Monopole in a periodic box: uniform points."""
     return uniform_box(n, box, seed=1001)
 
 
-def config2(n_centres: int = 10_000, per_blob: int = 100, n_rand: int = 2_000_000,
+def clustered_box_1e6(n_centres: int = 10_000, per_blob: int = 100, n_rand: int = 2_000_000,
             box: float = 2000.0, sigma: float = 5.0):
     """r-mu workload: clustered data (Gaussian blobs, not wrapped) and uniform
     randoms in an open box. Returns (data, randoms)."""
@@ -267,7 +270,7 @@ def config2(n_centres: int = 10_000, per_blob: int = 100, n_rand: int = 2_000_00
     return d, r
 
 
-def config3(n_data: int = 3_000_000, n_rand: int = 6_000_000, ra_max_deg: float = 60.0,
+def lightcone_3e6(n_data: int = 3_000_000, n_rand: int = 6_000_000, ra_max_deg: float = 60.0,
             dec_max_deg: float = 30.0):
     """sigma-pi light-cone workload. Returns (data, randoms)."""
     d = sky_cap_lightcone(n_data, seed=3001, ra_max_deg=ra_max_deg, dec_max_deg=dec_max_deg)
@@ -279,7 +282,7 @@ CAP_HALF_ANGLE_DEG = 40.75   # about 5000 sq-deg
 CAP_CENTRE = (180.0, 0.0)    # (RA, Dec) in degrees
 
 
-def config4(n_centres: int = 100_000, per_blob: int = 100, n_rand: int = 20_000_000,
+def angular_cap_1e7(n_centres: int = 100_000, per_blob: int = 100, n_rand: int = 20_000_000,
             half_angle_deg: float = CAP_HALF_ANGLE_DEG, centre=CAP_CENTRE,
             sigma_deg: float = 0.05):
     """Angular workload: clustered data and uniform randoms (unit vectors) in a
@@ -290,7 +293,7 @@ def config4(n_centres: int = 100_000, per_blob: int = 100, n_rand: int = 20_000_
     return d, r
 
 
-def config5(n_mocks: int = 256, n_lo: float = 2e4, n_hi: float = 5e5,
+def batched_mocks_256(n_mocks: int = 256, n_lo: float = 2e4, n_hi: float = 5e5,
             jk_base: int = 1_000_000, box: float = 1000.0):
     """Batched mocks: sizes log-uniform in [n_lo, n_hi], half uniform half blobs,
     periodic; plus one jackknife base catalog and its 10x10 (x, y) column region

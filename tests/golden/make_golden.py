@@ -22,20 +22,20 @@ import oracle  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def c2_binning():
+def rmu_binning():
     return (np.arange(41) * 5.0, np.arange(51) / 50.0)
 
 
-def make_c2_dd_rmu():
-    d, _ = catalogs.config2()
-    re_, me = c2_binning()
+def make_clustered_1e6_dd_rmu():
+    d, _ = catalogs.clustered_box_1e6()
+    re_, me = rmu_binning()
     t = time.time()
     h = oracle.count_pairs(d, None, oracle.Binning(oracle.RMU, re_, me, los=oracle.LOS_Z),
                            prune=True)
     return {
         "workload": "r-mu DD, 1e6 clustered points (1e4 Gaussian blobs of 100, sigma 5) in an "
                     "open 2000^3 box, r in [0,200) 40 bins, mu in [0,1] 50 bins, line of sight z",
-        "generator": "catalogs.config2() data catalog",
+        "generator": "catalogs.clustered_box_1e6() data catalog",
         "sha256": catalogs.sha256_of(d),
         "n": len(d),
         "r_edges": re_.tolist(),
@@ -45,15 +45,15 @@ def make_c2_dd_rmu():
     }
 
 
-def make_c1_dd_mono():
-    c = catalogs.config1()
+def make_periodic_2e4_dd_mono():
+    c = catalogs.periodic_uniform_2e4()
     e = np.arange(31) * 5.0
     t = time.time()
     h = oracle.count_pairs(c, None, oracle.Binning(oracle.MONO, e, periodic=True, L=1000.0))
     return {
         "workload": "monopole DD, 20000 uniform points in a periodic 1000^3 box, r in [0,150) "
                     "30 bins (brute force over all pairs)",
-        "generator": "catalogs.config1()",
+        "generator": "catalogs.periodic_uniform_2e4()",
         "sha256": catalogs.sha256_of(c),
         "n": len(c),
         "r_edges": e.tolist(),
@@ -62,7 +62,8 @@ def make_c1_dd_mono():
     }
 
 
-MAKERS = {"c1_dd_mono": make_c1_dd_mono, "c2_dd_rmu": make_c2_dd_rmu}
+MAKERS = {"periodic_2e4_dd_mono": make_periodic_2e4_dd_mono,
+          "clustered_1e6_dd_rmu": make_clustered_1e6_dd_rmu}
 
 
 if __name__ == "__main__":

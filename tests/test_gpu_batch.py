@@ -56,7 +56,7 @@ def grid(cat):
 @pytest.fixture(scope="module")
 def small():
     """6 mocks (500 .. 4000 points), a 6000-point jackknife base, its regions."""
-    mocks, base, region = catalogs.config5(n_mocks=6, n_lo=500, n_hi=4000, jk_base=6000, box=L)
+    mocks, base, region = catalogs.batched_mocks_256(n_mocks=6, n_lo=500, n_hi=4000, jk_base=6000, box=L)
     return mocks, base, region
 
 
@@ -186,7 +186,7 @@ def test_c5_shaped_batch_matches_single_and_jackknife_identity():
     its single count; the smallest mock equals the oracle; each jackknife
     catalog satisfies DD(base) = DD(rest) + DD(region) + DR(rest, region)."""
     import torch
-    mocks, base, region = catalogs.config5(n_mocks=24, n_lo=2e4, n_hi=1e5, jk_base=300_000, box=L)
+    mocks, base, region = catalogs.batched_mocks_256(n_mocks=24, n_lo=2e4, n_hi=1e5, jk_base=300_000, box=L)
     mono, rmu = bins()
     gm = [grid(m) for m in mocks]
     gb, gb2 = grid(base), grid(base)

@@ -51,7 +51,7 @@ def test_sigmapi_lightcone_full_size():
     """3e6 data and 6e6 randoms in the light cone; sigma and pi edges 2k Mpc/h
     (k <= 75), midpoint line of sight."""
     say("generating the light-cone catalogs")
-    d, r = catalogs.config3()
+    d, r = catalogs.lightcone_3e6()
     e = np.arange(76) * 2.0
     bn = cute.Binning(cute.BIN_SIGMAPI, e, e, los=cute.LOS_MIDPOINT)
     ob = oracle.Binning(oracle.SIGMAPI, e, e, los=oracle.LOS_MID)
@@ -80,7 +80,7 @@ def test_theta_cap_full_size():
     """1e7 clustered data and 2e7 randoms in a 5000 sq-deg cap; 30 log bins of
     theta in [0.001, 10] degrees."""
     say("generating the angular catalogs")
-    d, r = catalogs.config4()
+    d, r = catalogs.angular_cap_1e7()
     e = np.deg2rad(0.001 * 10.0 ** (np.arange(31) * 4.0 / 30.0))
     bn = cute.Binning(cute.BIN_THETA, e)
     ob = oracle.Binning(oracle.THETA, e)
@@ -116,7 +116,7 @@ def test_batched_mocks_and_jackknife_full_size():
     import torch
     L = 1000.0
     say("generating the batched workload")
-    mocks, base, region = catalogs.config5()
+    mocks, base, region = catalogs.batched_mocks_256()
     mono = cute.Binning(cute.BIN_MONO, np.arange(31) * 5.0)
     rmu = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(51) / 50.0, los=cute.LOS_Z)
     gm = [dgrid(m, cute.GEOM_BOX_PERIODIC, 200.0, L) for m in mocks]
@@ -161,7 +161,7 @@ def test_rmu_dr_rr_full_size_and_estimators():
     import os
 
     from oracle import estimators as est
-    d, r = catalogs.config2()
+    d, r = catalogs.clustered_box_1e6()
     e1, e2 = np.arange(41) * 5.0, np.arange(51) / 50.0
     bn = cute.Binning(cute.BIN_RMU, e1, e2, los=cute.LOS_Z)
     ob = oracle.Binning(oracle.RMU, e1, e2, los=oracle.LOS_Z)
@@ -179,7 +179,7 @@ def test_rmu_dr_rr_full_size_and_estimators():
     np.testing.assert_array_equal(dr, cute.count_pairs(gd, gr, bn, cute.PREC_FP64))
     rr = cute.count_pairs(gr, None, bn, cute.PREC_FP32_EDGE)
     np.testing.assert_array_equal(rr, cute.count_pairs(gr, None, bn, cute.PREC_FP64))
-    golden = os.path.join(os.path.dirname(__file__), "golden", "c2_dd_rmu.json")
+    golden = os.path.join(os.path.dirname(__file__), "golden", "clustered_1e6_dd_rmu.json")
     with open(golden) as f:
         dd = np.array(json.load(f)["counts"], dtype=np.uint64).reshape(bn.shape)
     nd, nr = len(d), len(r)

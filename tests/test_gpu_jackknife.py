@@ -44,7 +44,7 @@ def bins_periodic():
 
 
 def test_jackknife_periodic_columns_match_oracle():
-    _, base, region = catalogs.config5(n_mocks=1, n_lo=100, n_hi=200, jk_base=5000, box=L)
+    _, base, region = catalogs.batched_mocks_256(n_mocks=1, n_lo=100, n_hi=200, jk_base=5000, box=L)
     g = cute.build_grid(base, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0)
     for bn, ob in bins_periodic():
         want_total = oracle.count_pairs(base, None, ob).reshape(-1)
@@ -66,7 +66,7 @@ def test_jackknife_periodic_columns_match_oracle():
 
 
 def test_jackknife_open_box_slabs_and_edge_cases():
-    d, _ = catalogs.config2(n_centres=120, per_blob=30, n_rand=10, box=300.0)
+    d, _ = catalogs.clustered_box_1e6(n_centres=120, per_blob=30, n_rand=10, box=300.0)
     # 7 slabs in x, one of them empty
     xs = (d.x - d.x.min()) / (d.x.max() - d.x.min() + 1e-9)
     region = np.minimum((xs * 6).astype(np.int32), 5)

@@ -81,15 +81,16 @@ def test_mono_periodic_auto_and_cross():
     check_case("mono-periodic-cross", a, b, cute.BIN_MONO, e, geom=cute.GEOM_BOX_PERIODIC, L=300.0)
 
 
-def test_mono_periodic_config1_full_size():
-    """Config 1 at its full size, against the oracle's brute force."""
-    with open(os.path.join(GOLDEN, "c1_dd_mono.json")) as f:
+def test_mono_periodic_2e4_full_size():
+    """20 000 uniform points in a periodic box of side 1000 at full size,
+    against the oracle's brute force."""
+    with open(os.path.join(GOLDEN, "periodic_2e4_dd_mono.json")) as f:
         g = json.load(f)
-    c = catalogs.config1()
+    c = catalogs.periodic_uniform_2e4()
     assert catalogs.sha256_of(c) == g["sha256"]
     bn = cute.Binning(cute.BIN_MONO, np.array(g["r_edges"]))
     for prec in EXACT:
-        say("case config1 prec", prec)
+        say("case periodic-2e4 prec", prec)
         got = gpu_counts(c, None, bn, prec, cute.GEOM_BOX_PERIODIC, L=1000.0, r_max=150.0)
         np.testing.assert_array_equal(got, np.array(g["counts"], dtype=np.uint64))
 
@@ -99,9 +100,9 @@ def test_rmu_dd_full_size_benchmark_workload():
     40 x 50 bins) in the benchmark's launch configuration, against the
     oracle's counts stored by tests/golden/make_golden.py."""
     import torch
-    with open(os.path.join(GOLDEN, "c2_dd_rmu.json")) as f:
+    with open(os.path.join(GOLDEN, "clustered_1e6_dd_rmu.json")) as f:
         g = json.load(f)
-    d, _ = catalogs.config2()
+    d, _ = catalogs.clustered_box_1e6()
     assert catalogs.sha256_of(d) == g["sha256"], "generator output changed"
     want = np.array(g["counts"], dtype=np.uint64)
     dev = torch.device("cuda:0")
@@ -121,14 +122,14 @@ def test_rmu_dd_full_size_benchmark_workload():
 
 @pytest.mark.parametrize("cell", [0.0, 7.0, 33.0])
 def test_mono_open_log_bins(cell):
-    d, r = catalogs.config2(n_centres=120, per_blob=40, n_rand=8000, box=250.0)
+    d, r = catalogs.clustered_box_1e6(n_centres=120, per_blob=40, n_rand=8000, box=250.0)
     e = np.geomspace(0.2, 40.0, 21)
     check_case("mono-open-log-auto-%g" % cell, d, None, cute.BIN_MONO, e, cell=cell)
     check_case("mono-open-log-cross-%g" % cell, d, r, cute.BIN_MONO, e, cell=cell)
 
 
 def test_rmu_z_dd_dr_rr():
-    d, r = catalogs.config2(n_centres=150, per_blob=40, n_rand=15000, box=300.0)
+    d, r = catalogs.clustered_box_1e6(n_centres=150, per_blob=40, n_rand=15000, box=300.0)
     re_, me = np.linspace(0, 40, 9), np.linspace(0, 1, 11)
     check_case("rmu-dd", d, None, cute.BIN_RMU, re_, me)
     check_case("rmu-dr", d, r, cute.BIN_RMU, re_, me)
@@ -136,12 +137,12 @@ def test_rmu_z_dd_dr_rr():
 
 
 def test_rmu_z_partial_mu_range_and_rmin():
-    d, r = catalogs.config2(n_centres=100, per_blob=30, n_rand=6000, box=200.0)
+    d, r = catalogs.clustered_box_1e6(n_centres=100, per_blob=30, n_rand=6000, box=200.0)
     check_case("rmu-partial", d, r, cute.BIN_RMU, np.linspace(2, 30, 8), np.linspace(0.1, 0.9, 9))
 
 
 def test_rmu_midpoint_and_sigmapi_lightcone():
-    d, r = catalogs.config3(n_data=6000, n_rand=9000, ra_max_deg=5.0, dec_max_deg=4.0)
+    d, r = catalogs.lightcone_3e6(n_data=6000, n_rand=9000, ra_max_deg=5.0, dec_max_deg=4.0)
     e = np.linspace(0, 40, 21)
     check_case("rmu-mid-dd", d, None, cute.BIN_RMU, e, np.linspace(0, 1, 11), los=cute.LOS_MIDPOINT)
     check_case("rmu-mid-dr", d, r, cute.BIN_RMU, e, np.linspace(0, 1, 11), los=cute.LOS_MIDPOINT)
@@ -152,7 +153,7 @@ def test_rmu_midpoint_and_sigmapi_lightcone():
 @pytest.mark.parametrize("centre", [(180.0, 0.0), (0.0, 10.0), (45.0, 89.0), (300.0, -88.5)])
 def test_theta_caps(centre):
     """Equatorial cap, a cap straddling RA = 0 and caps around both poles."""
-    d, r = catalogs.config4(n_centres=60, per_blob=50, n_rand=9000, half_angle_deg=3.0,
+    d, r = catalogs.angular_cap_1e7(n_centres=60, per_blob=50, n_rand=9000, half_angle_deg=3.0,
                             centre=centre)
     e = np.deg2rad(np.geomspace(0.001, 2.0, 16))
     check_case("theta-dd-%s" % (centre,), d, None, cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
@@ -219,7 +220,7 @@ def test_periodic_pairs_across_faces():
 # Properties that hold at any size
 # ---------------------------------------------------------------------------
 def test_symmetry_and_fp32_only_bound():
-    d, r = catalogs.config2(n_centres=200, per_blob=50, n_rand=20000, box=400.0)
+    d, r = catalogs.clustered_box_1e6(n_centres=200, per_blob=50, n_rand=20000, box=400.0)
     bn = cute.Binning(cute.BIN_RMU, np.linspace(0, 50, 11), np.linspace(0, 1, 21))
     ga, gb = cute.build_grid(d, cute.GEOM_BOX_OPEN, r_max=50.0), cute.build_grid(r, cute.GEOM_BOX_OPEN, r_max=50.0)
     say("case symmetry")
@@ -280,7 +281,7 @@ def test_multipoles_match_exact_rationals():
 def test_tuned_grid_counts_match_oracle():
     """The grid tuner returns one of its (cell, tile) candidates with a time for
     each; counting with the chosen pair gives the oracle's counts."""
-    d, _ = catalogs.config2(n_centres=150, per_blob=40, n_rand=10, box=300.0)
+    d, _ = catalogs.clustered_box_1e6(n_centres=150, per_blob=40, n_rand=10, box=300.0)
     re_, me = np.linspace(0, 40, 9), np.linspace(0, 1, 11)
     bn = cute.Binning(cute.BIN_RMU, re_, me)
     cell, tile, times = cute.tune_grid(d, cute.GEOM_BOX_OPEN, bn)

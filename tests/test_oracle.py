@@ -198,7 +198,7 @@ def test_edge_cases_single_pairs():
 def test_periodic_uniform_matches_analytic_rr():
     """Uniform points in a periodic box: E[DD_k] = C(N,2) V_k/L^3 and the pair
     indicators are pairwise uncorrelated, so Var = C(N,2) p_k (1 - p_k)."""
-    cat = catalogs.config1()
+    cat = catalogs.periodic_uniform_2e4()
     n, L = len(cat), 1000.0
     edges = np.arange(31) * 5.0
     h = oracle.count_pairs(cat, None, Binning(MONO, edges, periodic=True, L=L), prune=True)
@@ -279,7 +279,7 @@ def test_symmetry_and_auto_cross_identity(periodic):
 
 
 def test_rmu_marginal_equals_mono():
-    d, r = catalogs.config2(n_centres=40, per_blob=25, n_rand=800, box=120.0)
+    d, r = catalogs.clustered_box_1e6(n_centres=40, per_blob=25, n_rand=800, box=120.0)
     re = np.linspace(0, 20, 9)
     mono = oracle.count_pairs(d, None, Binning(MONO, re))
     for los in (LOS_Z, LOS_MID):
@@ -310,13 +310,13 @@ def test_window_prune_equals_brute_force(kind):
         b = catalogs.uniform_box(2000, 100.0, seed=52)
         bn = Binning(MONO, np.linspace(0, 30, 16), periodic=True, L=100.0)
     elif kind == "rmu_open":
-        a, b = catalogs.config2(n_centres=30, per_blob=100, n_rand=3000, box=200.0)
+        a, b = catalogs.clustered_box_1e6(n_centres=30, per_blob=100, n_rand=3000, box=200.0)
         bn = Binning(RMU, np.linspace(0, 25, 6), np.linspace(0, 1, 11), los=LOS_Z)
     elif kind == "sigmapi":
-        a, b = catalogs.config3(n_data=2000, n_rand=2500, ra_max_deg=4.0, dec_max_deg=3.0)
+        a, b = catalogs.lightcone_3e6(n_data=2000, n_rand=2500, ra_max_deg=4.0, dec_max_deg=3.0)
         bn = Binning(SIGMAPI, np.linspace(0, 30, 16), np.linspace(0, 30, 16), los=LOS_MID)
     else:
-        a, b = catalogs.config4(n_centres=30, per_blob=50, n_rand=2500, half_angle_deg=5.0)
+        a, b = catalogs.angular_cap_1e7(n_centres=30, per_blob=50, n_rand=2500, half_angle_deg=5.0)
         bn = Binning(THETA, np.deg2rad(np.geomspace(0.001, 2.0, 12)))
     for bb in (None, b):
         full = oracle.count_pairs(a, bb, bn, prune=False)

@@ -40,7 +40,7 @@ def test_proportional_counts_give_zero():
 
 
 def test_box_estimator_is_unbiased_for_uniform_points():
-    cat = catalogs.config1()
+    cat = catalogs.periodic_uniform_2e4()
     edges = np.arange(31) * 5.0
     dd = oracle.count_pairs(cat, None, Binning(MONO, edges, periodic=True, L=1000.0), prune=True)
     xi = est.box(dd, len(cat), 1000.0, edges)

@@ -6,7 +6,8 @@ The oracle cannot count these catalogs whole, so the checks are
     whole other catalog (the rows of DR and DD that those points own), which
     the oracle computes one home point set at a time, bit-exact;
   * properties that hold at any size: the FP32_EDGE counts equal the FP64
-    counts of the same full-size autocorrelation.
+    counts of the same full-size counts (sigma-pi DD, DR and RR; the angular
+    DD).
 Inputs are the full-size seeded catalogs of the three workloads."""
 import sys
 
@@ -67,13 +68,14 @@ def test_sigmapi_lightcone_full_size():
             say("sigma-pi full size: %s prec %d" % (name, prec))
             got = cute.count_pairs(gs, go, bn, prec)
             np.testing.assert_array_equal(got, want, err_msg="%s prec %d" % (name, prec))
-    say("sigma-pi full size: DD FP32_EDGE vs FP64")
-    c32, st = cute.count_pairs(gd, None, bn, cute.PREC_FP32_EDGE, with_stats=True)
-    c64 = cute.count_pairs(gd, None, bn, cute.PREC_FP64)
-    np.testing.assert_array_equal(c32, c64)
-    say("sigma-pi full size: DD %d pairs in range, %d evaluations, %.1f ms"
-        % (st["pairs_in_range"], st["pair_evals"], st["ms_count"]))
-    assert st["pairs_in_range"] > 0
+    for name, ga, gb in (("DD", gd, None), ("DR", gd, gr), ("RR", gr, None)):
+        say("sigma-pi full size: %s FP32_EDGE vs FP64" % name)
+        c32, st = cute.count_pairs(ga, gb, bn, cute.PREC_FP32_EDGE, with_stats=True)
+        c64 = cute.count_pairs(ga, gb, bn, cute.PREC_FP64)
+        np.testing.assert_array_equal(c32, c64, err_msg=name)
+        say("sigma-pi full size: %s %d pairs in range, %d evaluations, %.1f ms"
+            % (name, st["pairs_in_range"], st["pair_evals"], st["ms_count"]))
+        assert st["pairs_in_range"] > 0
 
 
 def test_theta_cap_full_size():
@@ -95,12 +97,10 @@ def test_theta_cap_full_size():
             say("theta full size: %s prec %d" % (name, prec))
             got = cute.count_pairs(gs, go, bn, prec)
             np.testing.assert_array_equal(got, want, err_msg="%s prec %d" % (name, prec))
-    # the full autocorrelation of a tenth of the data: FP32_EDGE == FP64
-    sub = sample(d, len(d) // 10, seed=42)
-    gsub = dgrid(sub, cute.GEOM_SPHERE, e[-1])
-    say("theta full size: DD of %d points, FP32_EDGE vs FP64" % len(sub))
-    c32, st = cute.count_pairs(gsub, None, bn, cute.PREC_FP32_EDGE, with_stats=True)
-    c64 = cute.count_pairs(gsub, None, bn, cute.PREC_FP64)
+    # the full 1e7-point autocorrelation: FP32_EDGE == FP64
+    say("theta full size: DD of %d points, FP32_EDGE vs FP64" % len(d))
+    c32, st = cute.count_pairs(gd, None, bn, cute.PREC_FP32_EDGE, with_stats=True)
+    c64 = cute.count_pairs(gd, None, bn, cute.PREC_FP64)
     np.testing.assert_array_equal(c32, c64)
     say("theta: %d pairs in range, %d evaluations, %.1f ms"
         % (st["pairs_in_range"], st["pair_evals"], st["ms_count"]))

@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched mock/jackknife workload")
     ap.add_argument("--no-tune", action="store_true", help="skip the cell-size tuner leg")
+    ap.add_argument("--no-xi", action="store_true",
+                    help="skip the full xi(r, mu) time-to-solution leg (DD + DR + RR)")
     ap.add_argument("--no-table2", action="store_true",
                     help="skip the correlation functions of the paper's Table 2")
     ap.add_argument("--cell-size", type=float, default=0.0,
@@ -439,6 +441,9 @@ def main():
                      "traffic": committed_traffic(),
                      "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
     }
+    if not args.no_xi:
+        log("bench: full xi(r, mu): DD, DR, RR, Landy-Szalay, multipoles")
+        out["xi_rmu_full"] = xi_leg(cute, torch, dev, xyz, bn, c32)
     # the cell-size tuner on the same data: its choice and the count time with it
     if not args.no_tune:
         out["tuned_cell"] = tuned_leg(cute, xyz, bn, counts, c32)
@@ -451,6 +456,40 @@ def main():
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
+
+
+def xi_leg(cute, torch, dev, xyz, bn, c_dd, reps=3):
+    """Time to solution of the whole r-mu correlation function of the
+    benchmark workload: grids of the 1e6 data and 2e6 randoms, DD, DR and RR
+    (FP32_EDGE, counts in device memory), then the Landy-Szalay estimator
+    and the multipoles l = 0, 2, 4 on the host. Inputs resident in HBM."""
+    import catalogs
+    _, r = catalogs.clustered_box_1e6()
+    rxyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (r.x, r.y, r.z)]
+    outs = [torch.zeros(bn.nbins, dtype=torch.int64, device=dev) for _ in range(3)]
+    best, parts = None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gd = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0)
+        gr = cute.build_grid(rxyz, cute.GEOM_BOX_OPEN, r_max=200.0)
+        sts = [cute.count_pairs(a, b, bn, cute.PREC_FP32_EDGE, out=o, with_stats=True)[1]
+               for (a, b), o in zip(((gd, None), (gd, gr), (gr, None)), outs)]
+        dd, dr, rr = (o.cpu().numpy().astype(np.uint64).reshape(bn.shape) for o in outs)
+        xi = cute.xi_estimate(cute.EST_LS, dd, dr, rr, len(xyz[0]), len(rxyz[0]), bn)
+        mp = cute.xi_multipoles(np.nan_to_num(xi), bn, (0, 2, 4))
+        dt = (time.perf_counter() - t0) * 1e3
+        gd.close()
+        gr.close()
+        if best is None or dt < best:
+            best, parts = dt, sts
+    assert np.all(np.isfinite(mp))
+    evals = sum(int(s["pair_evals"]) for s in parts)
+    return {"ms": round(best, 3), "kernel_ms": {k: round(s["ms_count"], 3) for k, s in
+                                                zip(("dd", "dr", "rr"), parts)},
+            "pair_evals": evals, "gpair_evals_per_s": round(evals / (best * 1e-3) / 1e9, 1),
+            "dd_equals_headline": bool(np.array_equal(dd.reshape(-1), c_dd)),
+            "n_data": len(xyz[0]), "n_randoms": len(rxyz[0])}
 
 
 def tuned_leg(cute, xyz, bn, counts, c32):

@@ -201,3 +201,19 @@ def test_pixel_maps_are_rejected_where_unsupported():
     with pytest.raises(cute.CuteError) as e:
         cute.build_pixel_map(v * 2.0, 64, 64)
     assert e.value.status == cute.E_INVALID_ARG
+
+
+def test_weighted_counts_into_device_memory():
+    """Weighted counts written to a device tensor (the same-pixel pairs
+    included) equal the host copy."""
+    import torch
+    d = cap(8000, 3.0, 15, blobs=80)
+    g = cute.build_pixel_map(d, 1800, 3600, r_max=np.deg2rad(2.0))
+    bn = cute.Binning(cute.BIN_THETA, np.deg2rad(np.linspace(0.0, 2.0, 11)))
+    host = cute.count_pairs(g, None, bn, cute.PREC_FP32_EDGE)
+    out = torch.zeros(bn.nbins, dtype=torch.int64, device="cuda")
+    cute.count_pairs(g, None, bn, cute.PREC_FP32_EDGE, out=out)
+    np.testing.assert_array_equal(out.cpu().numpy().astype(np.uint64), host)
+    od = oracle.pixel_map(d, 1800, 3600)
+    np.testing.assert_array_equal(host, oracle.count_weighted(od, od.counts, None, None,
+                                                              oracle.Binning(oracle.THETA, bn.edges1)))

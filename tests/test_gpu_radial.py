@@ -159,3 +159,15 @@ def test_radial_rejections():
         with pytest.raises(cute.CuteError) as ex:
             f()
         assert ex.value.status == status
+
+
+def test_radial_counts_into_device_memory():
+    """Counts written to a device tensor equal the host copy."""
+    import torch
+    d, zd = patch(5000, 12, blobs=50)
+    g = grid(d, np.deg2rad(1.0))
+    e = np.linspace(0.0, 0.02, 11)
+    host = cute.count_radial(g, zd, None, None, np.deg2rad(1.0), e)
+    out = torch.zeros(len(e) - 1, dtype=torch.int64, device="cuda")
+    cute.count_radial(g, torch.from_numpy(zd).cuda(), None, None, np.deg2rad(1.0), e, out=out)
+    np.testing.assert_array_equal(out.cpu().numpy().astype(np.uint64), host)

@@ -248,7 +248,9 @@ cute_status cute_count_radial(const cute_grid* a, const double* ra, const cute_g
  *   {0, r/2, r/3, r/4, r/5, r/6} with r the binning's reach (theta in
  *   radians for SPHERE).
  * tiles: n_tile tile sizes in 1..64; n_tile == 0 uses {32, 64}.
- * best_cell, best_tile: the fastest pair. ms (nullable): the time of each
+ * best_cell, best_tile: the fastest pair, or, among the pairs within 2 % of
+ *   the fastest time (run-to-run noise), the one with the largest tile size
+ *   and then the first cell side in the candidate order. ms (nullable): the time of each
  *   pair, cell-major (n_cell x n_tile entries with the defaults' counts when
  *   0 is given; NaN for a pair the geometry rejects).
  * Errors: those of cute_build_grid and cute_count_pairs; CUTE_E_INVALID_ARG

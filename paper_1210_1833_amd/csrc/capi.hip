@@ -362,8 +362,8 @@ extern "C" cute_status cute_tune_grid(const double* x, const double* y, const do
     // tracks throughput, not the longest single tile
     const uint32_t sample = 32768;
     std::vector<uint64_t> counts((size_t)pl.a.nbins);
+    std::vector<double> tms(cand.size() * tsz.size(), INFINITY);
     double best_ms = INFINITY;
-    int best_i = -1;
     for (size_t i = 0; i < cand.size() * tsz.size(); i++) {
         cute_grid_params q = *p;
         q.cell_size = cand[i / tsz.size()];
@@ -384,12 +384,24 @@ extern "C" cute_status cute_tune_grid(const double* x, const double* y, const do
         }
         if (s == CUTE_E_OUT_OF_MEMORY || s == CUTE_E_DEVICE) return s;
         if (ms) ms[i] = s == CUTE_OK ? t : NAN;  // a rejected pair is NaN
-        if (s == CUTE_OK && t < best_ms) {
-            best_ms = t;
-            best_i = (int)i;
+        if (s == CUTE_OK) {
+            tms[i] = t;
+            best_ms = std::min(best_ms, t);
         }
     }
-    if (best_i < 0) return fail(CUTE_E_INVALID_ARG, "no candidate is usable");
+    if (!std::isfinite(best_ms)) return fail(CUTE_E_INVALID_ARG, "no candidate is usable");
+    // timings differ by a percent or two from run to run: among the pairs
+    // within 2 % of the fastest, take the largest tile, then the first cell
+    // side in the candidate order, so that the choice is stable
+    int best_i = -1;
+    std::vector<size_t> tord(tsz.size());
+    for (size_t k = 0; k < tsz.size(); k++) tord[k] = k;
+    std::stable_sort(tord.begin(), tord.end(), [&](size_t u, size_t v) { return tsz[u] > tsz[v]; });
+    for (size_t k = 0; k < tord.size() && best_i < 0; k++)
+        for (size_t c = 0; c < cand.size() && best_i < 0; c++) {
+            const size_t i = c * tsz.size() + tord[k];
+            if (tms[i] <= best_ms * 1.02) best_i = (int)i;
+        }
     *best_cell = cand[best_i / tsz.size()];
     *best_tile = tsz[best_i % tsz.size()];
     return CUTE_OK;

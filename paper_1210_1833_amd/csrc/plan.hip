@@ -265,7 +265,7 @@ cute_status plan_item(const GridHost& A, const GridHost& B, bool is_auto, const 
     } else if (sphere) {
         max_w = std::max(1, (int)std::floor(0.5 * g->th_s / A.ax));
     } else {
-        max_w = std::max(1, (int)std::floor(0.5 * g->Rs / A.ax));
+        max_w = std::max(1, (int)std::floor(0.5 * g->Rs / A.ax + 0.5));
     }
     g->max_w = std::min(max_w, 65535);
 

@@ -354,6 +354,24 @@ cute_status cute_count_jackknife(const cute_grid* g, const int32_t* region, int3
                                  uint64_t* total, uint64_t* jack, cute_count_stats* st,
                                  void* stream);
 
+/* The same for a cross-correlation (DR of the Landy-Szalay estimator, Sec.
+ * 2.2): jack_k counts the pairs between a without its region-k points and b
+ * without its region-k points. Three passes whatever K: the total, the pairs
+ * whose a point lies in region k (a's points as home), and the pairs whose b
+ * point lies in region k and whose a point does not (b's points as home);
+ * T_k is their sum and jack_k = total - T_k. Bit-exact like
+ * cute_count_pairs on each pair of catalogs.
+ * a, b: two different 3-D grids of one geometry kind; region_a, region_b:
+ * their labels in input order, each in [0, K) (device pointers if
+ * regions_on_device). total: the cross count of a and b; jack: K rows.
+ * Errors: those of cute_count_jackknife; CUTE_E_INVALID_ARG if a == b. */
+cute_status cute_count_jackknife_cross(const cute_grid* a, const int32_t* region_a,
+                                       const cute_grid* b, const int32_t* region_b,
+                                       int32_t regions_on_device, int32_t K,
+                                       const cute_binning* bins, cute_precision prec,
+                                       uint64_t* total, uint64_t* jack, cute_count_stats* st,
+                                       void* stream);
+
 /* Estimator of Sec. 2.2 per bin (xi has the shape of the counts).
  * NATURAL: dd, rr; LS: dd, dr, rr; BOX: dd only (MONO binning, periodic
  * volume box_size^3, expected count N(N-1)/2 * V_shell / L^3 with the exact

@@ -29,6 +29,7 @@ BATCH_GRAPH, BATCH_EAGER = range(2)
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
             "cute_tune_grid", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched", "cute_count_jackknife",
+            "cute_count_jackknife_cross",
             "cute_build_pixel_map", "cute_pixel_map_read", "cute_count_radial",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
 
@@ -122,6 +123,10 @@ def load():
     lib.cute_count_pairs_batched.argtypes = [ctypes.POINTER(CBatchItem), ctypes.c_int32,
                                              ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int32,
                                              ctypes.POINTER(CountStats), vp]
+    lib.cute_count_jackknife_cross.restype = ctypes.c_int
+    lib.cute_count_jackknife_cross.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(CBinning), ctypes.c_int, vp, vp,
+                                               ctypes.POINTER(CountStats), vp]
     lib.cute_count_jackknife.restype = ctypes.c_int
     lib.cute_count_jackknife.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.POINTER(CBinning), ctypes.c_int, vp, vp,
@@ -544,13 +549,8 @@ def count_pairs_batched(items, prec: int = PREC_FP32_EDGE, stream=None, with_sta
     return (res, st.as_dict()) if with_stats else res
 
 
-def count_jackknife(grid: Grid, region, n_regions: int, binning: Binning,
-                    prec: int = PREC_FP32_EDGE, stream=None, with_stats: bool = False):
-    """cute_count_jackknife: (total, jack) with jack[k] the autocorrelation of
-    the grid's catalog without the points of region k. ``region``: one label
-    in [0, n_regions) per point, in the grid's input order (numpy int32 on
-    the host or a torch int32 tensor on the device)."""
-    lib = load()
+def _labels(region, n):
+    """(pointer, on_device, keepalive) of int32 region labels, one per point."""
     try:
         import torch
         is_t = isinstance(region, torch.Tensor)
@@ -558,14 +558,44 @@ def count_jackknife(grid: Grid, region, n_regions: int, binning: Binning,
         is_t = False
     if is_t:
         reg = region.contiguous()
-        if reg.dtype != torch.int32 or reg.numel() != grid.n:
+        if reg.dtype != torch.int32 or reg.numel() != n:
             raise ValueError("region must be int32 with one label per point")
-        ptr, on_dev = reg.data_ptr(), int(reg.is_cuda)
-    else:
-        reg = np.ascontiguousarray(region, dtype=np.int32)
-        if reg.size != grid.n:
-            raise ValueError("region must have one label per point")
-        ptr, on_dev = reg.ctypes.data, 0
+        return reg.data_ptr(), int(reg.is_cuda), reg
+    reg = np.ascontiguousarray(region, dtype=np.int32)
+    if reg.size != n:
+        raise ValueError("region must have one label per point")
+    return reg.ctypes.data, 0, reg
+
+
+def count_jackknife_cross(a: Grid, region_a, b: Grid, region_b, n_regions: int,
+                          binning: Binning, prec: int = PREC_FP32_EDGE, stream=None,
+                          with_stats: bool = False):
+    """cute_count_jackknife_cross: (total, jack) with jack[k] the cross count
+    of a and b, both without their region-k points. Labels as for
+    count_jackknife, both on the host or both on the device."""
+    lib = load()
+    pa, da, ka = _labels(region_a, a.n)
+    pb, db, kb = _labels(region_b, b.n)
+    if da != db:
+        raise ValueError("region_a and region_b must both be on the host or both on the device")
+    total = np.zeros(binning.nbins, dtype=np.uint64)
+    jack = np.zeros((int(n_regions), binning.nbins), dtype=np.uint64)
+    st = CountStats()
+    _check(lib.cute_count_jackknife_cross(a.handle, pa, b.handle, pb, da, int(n_regions),
+                                          ctypes.byref(binning.c()), int(prec), total.ctypes.data,
+                                          jack.ctypes.data, ctypes.byref(st), _stream_handle(stream)))
+    res = (total.reshape(binning.shape), jack.reshape((int(n_regions),) + binning.shape))
+    return (res + (st.as_dict(),)) if with_stats else res
+
+
+def count_jackknife(grid: Grid, region, n_regions: int, binning: Binning,
+                    prec: int = PREC_FP32_EDGE, stream=None, with_stats: bool = False):
+    """cute_count_jackknife: (total, jack) with jack[k] the autocorrelation of
+    the grid's catalog without the points of region k. ``region``: one label
+    in [0, n_regions) per point, in the grid's input order (numpy int32 on
+    the host or a torch int32 tensor on the device)."""
+    lib = load()
+    ptr, on_dev, reg = _labels(region, grid.n)
     total = np.zeros(binning.nbins, dtype=np.uint64)
     jack = np.zeros((int(n_regions), binning.nbins), dtype=np.uint64)
     st = CountStats()

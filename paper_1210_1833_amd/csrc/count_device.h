@@ -417,11 +417,11 @@ __device__ __forceinline__ void lds_add(uint32_t byte_addr, uint64_t w) {
                            (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Weight of a pair in a region pass: 1 if the neighbour lies in the home
-// region, 2 otherwise (1 outside region passes).
+// Weight of a pair in a region pass: wsame if the neighbour lies in the home
+// region, wdiff otherwise (1 outside region passes).
 __device__ __forceinline__ uint32_t pair_weight(const CountArgs& P, uint32_t j) {
     if (P.regs == nullptr) return 1u;
-    return P.regs[j] == (uint16_t)P.region ? 1u : 2u;
+    return P.regs[j] == (uint16_t)P.region ? P.wsame : P.wdiff;
 }
 
 // Weight of the pair (home i, neighbour j): the product of the two point

@@ -110,11 +110,14 @@ struct CountArgs {
     // precomputed neighbour rows (see ItemGeom::stencil), or nullptr
     const int4* stencil;
     int nst;
-    // region pass of the jackknife (full stencil over one catalog): sorted-
-    // order region of each point, the home region of this item's tiles, and
-    // the j != i test in the home tile's own span; regs == nullptr otherwise
+    // region pass of the jackknife (full stencil): sorted-order region of
+    // each neighbour point, the home region of this item's tiles, the weights
+    // of a pair whose neighbour lies in the home region (wsame) or not
+    // (wdiff), and the j != i test in the home tile's own span when home and
+    // neighbours are one catalog; regs == nullptr otherwise (weight 1)
     const uint16_t* regs;
     int region;
+    uint32_t wsame, wdiff;
     int selfx;
     // point masks (batched counts): bit i of word i / 32 set = sorted point i
     // excluded; nullptr = no mask

@@ -201,3 +201,17 @@ def test_radial_rejects_bad_arguments(lib):
     dp = ctypes.POINTER(ctypes.c_double)
     assert lib.cute_count_radial(None, z.ctypes.data, None, None, 0, 0.01, 4, e.ctypes.data_as(dp),
                                  out.ctypes.data, 0, None, None) == cute.E_INVALID_ARG
+
+
+def test_jackknife_cross_rejects_bad_arguments(lib):
+    b = cute.Binning(cute.BIN_MONO, [0.0, 1.0, 2.0]).c()
+    reg = np.zeros(4, dtype=np.int32)
+    out = np.zeros(8, dtype=np.uint64)
+    fake = ctypes.c_void_p(1)
+    # NULL grids or labels, and a K out of range, are rejected before a grid is read
+    for ga, ra, gb, rb, k in ((None, reg, fake, reg, 2), (fake, None, fake, reg, 2),
+                              (fake, reg, None, reg, 2), (fake, reg, fake, None, 2),
+                              (fake, reg, fake, reg, 0), (fake, reg, fake, reg, 70000)):
+        assert lib.cute_count_jackknife_cross(
+            ga, None if ra is None else ra.ctypes.data, gb, None if rb is None else rb.ctypes.data,
+            0, k, ctypes.byref(b), 1, out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG

@@ -1,8 +1,9 @@
-"""GPU parity of the jackknife by region decomposition (cute_count_jackknife).
+"""GPU parity of the jackknife by region decomposition (cute_count_jackknife
+and, for cross-correlations, cute_count_jackknife_cross).
 
-Each jackknife row must equal the oracle's autocorrelation of the catalog
-without that region (bit-exact for FP64 and FP32_EDGE), the masked batched
-count of the same catalog, and the total the plain autocorrelation. Inputs:
+Each jackknife row must equal the oracle's count of the catalog(s) without
+that region (bit-exact for FP64 and FP32_EDGE), the masked batched count of
+the same catalog(s), and the total the plain count. Inputs:
 the batched mock workload's shapes (periodic box, half uniform half
 clustered, 10 x 10 column regions) and clustered data in an open box with
 slab regions, at sizes the oracle finishes in seconds."""
@@ -94,3 +95,65 @@ def test_jackknife_open_box_slabs_and_edge_cases():
     bad[5] = K
     with pytest.raises(cute.CuteError):
         cute.count_jackknife(g, bad, K, bn)
+
+
+def test_jackknife_cross_periodic_matches_oracle_and_masks():
+    """Cross jackknife (cute_count_jackknife_cross) of two periodic catalogs
+    with 10 x 10 column regions: every row equals the masked batched cross
+    count, sampled rows and the total equal the oracle."""
+    _, base, region = catalogs.batched_mocks_256(n_mocks=1, n_lo=100, n_hi=200, jk_base=4000, box=L)
+    other = catalogs.mixed_periodic(3000, L, seed=7101)
+    ix = np.minimum((other.x * (10.0 / L)).astype(np.int64), 9)
+    iy = np.minimum((other.y * (10.0 / L)).astype(np.int64), 9)
+    reg_b = (iy * 10 + ix).astype(np.int32)
+    ga = cute.build_grid(base, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0)
+    gb = cute.build_grid(other, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0)
+    for bn, ob in bins_periodic():
+        want_total = oracle.count_pairs(base, other, ob).reshape(bn.shape)
+        checked = [0, 7, 44, 99]
+        want = {k: oracle.count_pairs(base.subset(np.nonzero(region != k)[0]),
+                                      other.subset(np.nonzero(reg_b != k)[0]), ob).reshape(bn.shape)
+                for k in checked}
+        for prec in EXACT:
+            say("cross jackknife periodic, %d bins, prec %d" % (bn.nbins, prec))
+            total, jack = cute.count_jackknife_cross(ga, region, gb, reg_b, 100, bn, prec)
+            np.testing.assert_array_equal(total, want_total)
+            for k in checked:
+                np.testing.assert_array_equal(jack[k], want[k], err_msg="region %d" % k)
+            items = [cute.BatchItem(ga, gb, bn, mask_a=(region == k).astype(np.uint8),
+                                    mask_b=(reg_b == k).astype(np.uint8)) for k in range(100)]
+            got = cute.count_pairs_batched(items, prec)
+            for k in range(100):
+                np.testing.assert_array_equal(jack[k], got[k], err_msg="region %d" % k)
+
+
+def test_jackknife_cross_open_boxes_of_different_extent():
+    """Clustered data against uniform randoms in open boxes of different
+    bounding boxes (so the neighbour rows are derived per tile), 6 slab
+    regions with one empty in the randoms, against the oracle; device labels;
+    the same grid twice is rejected."""
+    import torch
+    d, r = catalogs.clustered_box_1e6(n_centres=100, per_blob=30, n_rand=4000, box=300.0)
+    reg_d = np.minimum(((d.x - d.x.min()) / (np.ptp(d.x) + 1e-9) * 6).astype(np.int32), 5)
+    reg_r = np.minimum(((r.x - r.x.min()) / (np.ptp(r.x) + 1e-9) * 6).astype(np.int32), 5)
+    reg_r[reg_r == 2] = 4             # region 2 of the randoms is empty
+    K = 6
+    e1, e2 = np.linspace(0, 40, 9), np.linspace(0, 1, 11)
+    bn = cute.Binning(cute.BIN_RMU, e1, e2)
+    ob = oracle.Binning(oracle.RMU, e1, e2, los=oracle.LOS_Z)
+    gd = cute.build_grid(d, cute.GEOM_BOX_OPEN, r_max=40.0)
+    gr = cute.build_grid(r, cute.GEOM_BOX_OPEN, r_max=40.0)
+    for prec in EXACT:
+        say("cross jackknife open boxes, prec %d" % prec)
+        total, jack = cute.count_jackknife_cross(gd, reg_d, gr, reg_r, K, bn, prec)
+        np.testing.assert_array_equal(total, oracle.count_pairs(d, r, ob))
+        for k in range(K):
+            want = oracle.count_pairs(d.subset(np.nonzero(reg_d != k)[0]),
+                                      r.subset(np.nonzero(reg_r != k)[0]), ob)
+            np.testing.assert_array_equal(jack[k], want, err_msg="region %d prec %d" % (k, prec))
+    t2, j2 = cute.count_jackknife_cross(gd, torch.from_numpy(reg_d).cuda(), gr,
+                                        torch.from_numpy(reg_r).cuda(), K, bn)
+    np.testing.assert_array_equal(j2, jack)
+    with pytest.raises(cute.CuteError) as ex:
+        cute.count_jackknife_cross(gd, reg_d, gd, reg_d, K, bn)
+    assert ex.value.status == cute.E_INVALID_ARG

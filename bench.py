@@ -156,6 +156,21 @@ def batched_leg(cute, torch, dev, runs=1):
             jk_ok = jk_ok and bool(np.array_equal(jack[k].reshape(-1), allc[o:o + w]))
         jk[name] = {"wall_ms": round(dt * 1e3, 2), "kernel_ms": round(jst["ms_count"], 2),
                     "pair_evals": int(jst["pair_evals"])}
+    # the DR jackknife of the same base against 1e6 uniform randoms with the
+    # same column regions (three passes whatever the number of regions)
+    rnd = catalogs.uniform_box(1_000_000, L, seed=5600)
+    rreg = (np.minimum((rnd.y * (10.0 / L)).astype(np.int64), 9) * 10
+            + np.minimum((rnd.x * (10.0 / L)).astype(np.int64), 9)).astype(np.int32)
+    grn = cute.build_grid([torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (rnd.x, rnd.y, rnd.z)],
+                          cute.GEOM_BOX_PERIODIC, box_size=L, r_max=200.0, cell_size=cb, tile_points=tb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, jst = cute.count_jackknife_cross(gb, reg_h, grn, rreg, 100, rmu, cute.PREC_FP32_EDGE,
+                                           with_stats=True)
+    dt = time.perf_counter() - t0
+    jk["r_mu_dr_vs_1e6_randoms"] = {"wall_ms": round(dt * 1e3, 2), "kernel_ms": round(jst["ms_count"], 2),
+                                    "pair_evals": int(jst["pair_evals"])}
+    grn.close()
     b.close()
     return {"jackknife_by_regions": dict(jk, bit_exact_vs_masked_batch=jk_ok,
                                          note="all 100 jackknife catalogs of the base, per binning"),

@@ -98,7 +98,10 @@ typedef struct {
     double r_max;      /* largest separation (radians for SPHERE) the grid
                           will be counted at; 0 = unknown. Used to size cells
                           and, for a periodic box, to keep the stencil free
-                          of duplicate images.                                */
+                          of duplicate images: a tile and its reach need at
+                          least 3 / (1 - 2 r_max / L) + 1 cells per axis
+                          (at most 406), so periodic counts reach up to
+                          about r_max = 0.496 L.                              */
     double cell_size;  /* cell side (pixel side in radians for SPHERE);
                           0 = chosen by the library                           */
     int32_t device_ptrs; /* nonzero: x, y, z are device pointers             */

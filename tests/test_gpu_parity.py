@@ -321,3 +321,35 @@ def test_table2_binnings(cell):
     du, ru = catalogs.unit_vectors(d), catalogs.unit_vectors(r)
     check_case("t2-theta-%g" % cell, du, ru, cute.BIN_THETA, np.deg2rad(np.linspace(0.0, 30.0, 257)),
                geom=cute.GEOM_SPHERE, cell=(1e9 if cell else 0.0))
+
+
+@pytest.mark.parametrize("offset", [1e5, 3e6])
+def test_far_from_the_origin_and_offset_grids(offset):
+    """Catalogs far from the origin (large raw coordinates, small
+    separations) and two grids whose boxes barely overlap (a large FP32 frame
+    shift between them): FP64 and FP32_EDGE equal the oracle for r-mu (z line
+    of sight) and sigma-pi (midpoint line of sight)."""
+    d, r = catalogs.clustered_box_1e6(n_centres=80, per_blob=30, n_rand=3000, box=150.0)
+    a = np.stack([d.x, d.y, d.z], axis=1) + offset
+    b = np.stack([r.x, r.y, r.z], axis=1) + offset + np.array([120.0, 0.0, 0.0])
+    check_case("far-rmu-auto-%g" % offset, a, None, cute.BIN_RMU, np.linspace(0, 30, 7),
+               np.linspace(0, 1, 6))
+    check_case("far-rmu-cross-%g" % offset, a, b, cute.BIN_RMU, np.linspace(0, 30, 7),
+               np.linspace(0, 1, 6))
+    e = np.linspace(0, 20, 6)
+    check_case("far-sigmapi-cross-%g" % offset, a, b, cute.BIN_SIGMAPI, e, e,
+               los=cute.LOS_MIDPOINT)
+
+
+def test_periodic_rmax_close_to_half_box():
+    """r_max = 0.49 L in a periodic box: every pair is still counted once
+    (minimum image), against the oracle. Closer to L/2 a tile and its reach
+    would need more cells than a grid may have: a clean CUTE_E_INVALID_ARG."""
+    L = 200.0
+    a = catalogs.mixed_periodic(3000, L, seed=131)
+    e = np.linspace(0.0, 0.49 * L, 12)
+    check_case("periodic-0.49L", a, None, cute.BIN_MONO, e, geom=cute.GEOM_BOX_PERIODIC, L=L)
+    g = cute.build_grid(a, cute.GEOM_BOX_PERIODIC, box_size=L, r_max=0.4995 * L)
+    with pytest.raises(cute.CuteError) as ex:
+        cute.count_pairs(g, None, cute.Binning(cute.BIN_MONO, np.linspace(0.0, 0.4995 * L, 5)))
+    assert ex.value.status == cute.E_INVALID_ARG

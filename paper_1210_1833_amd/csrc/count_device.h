@@ -319,8 +319,10 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         c.kb = est_bits(ts, P.e1a, T, P.top1);
         float w = v * ll;
         float sl2 = sl * sl;
-        float lnorm = __builtin_amdgcn_sqrtf(ll);
-        c.kmb = est_bits(fmaf(fabsf(sl), rinv * __builtin_amdgcn_rcpf(lnorm), P.s2), P.e2a, T, P.top2);
+        // 1/|l| once: |l| for the band and mu = |s.l| / (r |l|) for the estimate
+        float rl = __builtin_amdgcn_rsqf(ll);
+        float lnorm = ll * rl;
+        c.kmb = est_bits(fmaf(fabsf(sl), rinv * rl, P.s2), P.e2a, T, P.top2);
         float2 b = band_at(T.tb1, c.kb);
         float2 m = band_at(T.tb2, c.kmb);
         float delta = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, r, P.dA0)),
@@ -345,13 +347,15 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
     float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
     float sl2 = sl * sl;
     float c2 = fmaf(v, ll, -sl2);
-    float rll = __builtin_amdgcn_rcpf(ll);
-    float sg = __builtin_amdgcn_sqrtf(fmaxf(c2 * rll, 0.0f));
-    float pp = __builtin_amdgcn_sqrtf(sl2 * rll);
+    // sigma = sqrt(c2) / |l| and pi = |s.l| / |l| share one 1/|l|: three
+    // quarter-rate operations per pair (rsq, two sqrt) instead of five
+    float rl = __builtin_amdgcn_rsqf(ll);
+    float lnorm = ll * rl;
+    float sg = __builtin_amdgcn_sqrtf(fmaxf(c2, 0.0f)) * rl;
+    float pp = fabsf(sl) * rl;
     c.kb = est_bits(sg + P.s1, P.e1a, T, P.top1);
     c.kmb = est_bits(pp + P.s2, P.e2a, T, P.top2);
     float t = __builtin_amdgcn_sqrtf(v);
-    float lnorm = __builtin_amdgcn_sqrtf(ll);
     float ds = fmaf(ll, fmaf(P.sA2, v, fmaf(P.sA1, t, P.sA0)),
                     fmaf(lnorm, fmaf(P.sB2, v, fmaf(P.sB1, t, P.sB0)), fmaf(P.sC2, v, P.sC0)));
     float dp = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, t, P.dA0)),

@@ -353,3 +353,43 @@ def test_periodic_rmax_close_to_half_box():
     with pytest.raises(cute.CuteError) as ex:
         cute.count_pairs(g, None, cute.Binning(cute.BIN_MONO, np.linspace(0.0, 0.4995 * L, 5)))
     assert ex.value.status == cute.E_INVALID_ARG
+
+
+def test_concurrent_counts_on_two_streams():
+    """One grid counted from two host threads, each on its own stream, with
+    different binnings and precisions: every result equals the serial one."""
+    import threading
+
+    import torch
+    d, r = catalogs.clustered_box_1e6(n_centres=150, per_blob=40, n_rand=8000, box=300.0)
+    gd = cute.build_grid(d, cute.GEOM_BOX_OPEN, r_max=40.0)
+    gr = cute.build_grid(r, cute.GEOM_BOX_OPEN, r_max=40.0)
+    jobs = [(gd, None, cute.Binning(cute.BIN_RMU, np.linspace(0, 40, 9), np.linspace(0, 1, 11)),
+             cute.PREC_FP32_EDGE),
+            (gd, gr, cute.Binning(cute.BIN_MONO, np.geomspace(0.5, 40.0, 13)), cute.PREC_FP64),
+            (gr, None, cute.Binning(cute.BIN_MONO, np.linspace(0, 40, 21)), cute.PREC_FP32_EDGE),
+            (gd, gr, cute.Binning(cute.BIN_RMU, np.linspace(0, 40, 9), np.linspace(0, 1, 11)),
+             cute.PREC_FP32_EDGE)]
+    want = [cute.count_pairs(a, b, bn, p) for a, b, bn, p in jobs]
+    got = [[None] * len(jobs) for _ in range(2)]
+    errors = []
+
+    def worker(t):
+        try:
+            s = torch.cuda.Stream()
+            for rep in range(3):
+                for k in (range(len(jobs)) if t == 0 else reversed(range(len(jobs)))):
+                    a, b, bn, p = jobs[k]
+                    got[t][k] = cute.count_pairs(a, b, bn, p, stream=s)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for t in range(2):
+        for k in range(len(jobs)):
+            np.testing.assert_array_equal(got[t][k], want[k], err_msg="thread %d job %d" % (t, k))

@@ -220,9 +220,10 @@ cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_
  * the aperture, binned by the difference of their redshifts.
  * a, b: SPHERE grids of unit vectors (b == NULL or b == a: autocorrelation of
  *   a, pairs i < j); build them with r_max >= aperture for a tight stencil.
- * ra, rb: one redshift per object, in the order the coordinates were given to
- *   cute_build_grid (host or device memory as r_on_device says; rb unused for
- *   an autocorrelation); finite.
+ * ra, rb: one redshift per object (or any per-object scalar, such as the
+ *   comoving distance, to bin its difference), in the order the coordinates
+ *   were given to cute_build_grid (host or device memory as r_on_device says;
+ *   rb unused for an autocorrelation); finite.
  * aperture: radians in (0, pi]; a pair is aligned when its chord^2, formed
  *   from the FP64 differences of the unit vectors, is below
  *   (2 sin(aperture / 2))^2, i.e. theta < aperture.

@@ -124,7 +124,7 @@ typedef struct {
 
 typedef struct {
     uint64_t pair_evals;      /* candidate pairs evaluated by the kernels    */
-    uint64_t pairs_in_range;  /* sum of the counts                           */
+    uint64_t pairs_in_range;  /* sum of the counts (weighted for pixel maps) */
     uint64_t retests;         /* pairs re-tested in FP64 (FP32_EDGE)         */
     uint64_t flips;           /* re-tested pairs whose FP32 decision differed
                                  from the FP64 one (the FP32-only miscounts) */

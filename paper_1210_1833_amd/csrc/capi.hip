@@ -263,8 +263,13 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     } else {
         CUTE_HIP(hipMemcpyAsync(counts, work, (size_t)nbins * 8, hipMemcpyDeviceToHost, hs));
     }
-    unsigned long long hst[4] = {0, 0, 0, 0};
-    CUTE_HIP(hipMemcpyAsync(hst, work + nbins, sizeof(hst), hipMemcpyDeviceToHost, hs));
+    // the statistics, and with device counts and statistics asked for, a host
+    // copy of the counts for their sum (counts and statistics are adjacent)
+    const bool sum_dev = counts_on_device && st;
+    std::vector<unsigned long long> hw(sum_dev ? (size_t)nbins + 4 : 4, 0ull);
+    const unsigned long long* hst = hw.data() + (sum_dev ? nbins : 0);
+    CUTE_HIP(hipMemcpyAsync(hw.data(), sum_dev ? work : work + nbins, hw.size() * 8,
+                            hipMemcpyDeviceToHost, hs));
     CUTE_HIP(hipStreamSynchronize(hs));
     const double ms = ntiles > 0 ? timer.elapsed_ms() : 0.0;
     if (st) {
@@ -274,9 +279,8 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
         st->tiles = hst[3];
         st->ms_count = ms;
         uint64_t tot = 0;
-        if (!counts_on_device)
-            for (int k = 0; k < nbins; k++) tot += counts[k];
-        st->pairs_in_range = counts_on_device ? 0 : tot;
+        for (int k = 0; k < nbins; k++) tot += sum_dev ? (uint64_t)hw[k] : counts[k];
+        st->pairs_in_range = tot;
     }
     if (hst[3] != ntiles) return fail(CUTE_E_INTERNAL, "not every tile was processed");
     return CUTE_OK;

@@ -112,8 +112,9 @@ def test_rmu_dd_full_size_benchmark_workload():
     for prec in EXACT:
         say("case c2-full prec", prec)
         grid = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0)
-        cute.count_pairs(grid, None, bn, prec, out=out)
+        _, st = cute.count_pairs(grid, None, bn, prec, out=out, with_stats=True)
         np.testing.assert_array_equal(out.cpu().numpy().astype(np.uint64), want)
+        assert st["pairs_in_range"] == int(want.sum())
     # the FP32-only path misclassifies only a few pairs per million
     cute.count_pairs(grid, None, bn, cute.PREC_FP32_ONLY, out=out)
     l1 = int(np.abs(out.cpu().numpy() - want.astype(np.int64)).sum())

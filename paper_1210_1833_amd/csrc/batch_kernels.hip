@@ -154,6 +154,12 @@ __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict
         p[i] = 0ull;
 }
 
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 template <int MODE, int PREC, int EST>
 cute_status prep_one(size_t lds, int* per_cu) {
     auto kern = k_count_batch<MODE, PREC, EST>;
@@ -238,6 +244,15 @@ cute_status zero_u64(unsigned long long* p, size_t n, hipStream_t s) {
     size_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    CUTE_HIP(hipGetLastError());
+    return CUTE_OK;
+}
+
+cute_status zero_u32(uint32_t* p, size_t n, hipStream_t s) {
+    if (n == 0) return CUTE_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
     CUTE_HIP(hipGetLastError());
     return CUTE_OK;
 }

@@ -49,6 +49,66 @@ cute_status ensure_device_ready(int* device) {
     return CUTE_OK;
 }
 
+struct StageBuf {
+    unsigned char* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // recorded when the last lease ended
+    int dev = -1;               // device of the event
+};
+
+static std::mutex g_stage_mu;
+static std::vector<StageBuf*> g_stage_free;
+
+cute_status HostStage::get(size_t bytes, unsigned char** p) {
+    *p = nullptr;
+    if (!b_) {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (!g_stage_free.empty()) {
+            b_ = g_stage_free.back();
+            g_stage_free.pop_back();
+        }
+    }
+    if (!b_) {
+        b_ = new (std::nothrow) StageBuf;
+        if (!b_) return fail(CUTE_E_OUT_OF_MEMORY, "host allocation");
+    }
+    if (b_->done) CUTE_HIP(hipEventSynchronize(b_->done));
+    if (bytes > b_->cap) {
+        if (b_->p) (void)hipHostFree(b_->p);
+        b_->p = nullptr;
+        b_->cap = 0;
+        const size_t cap = std::max<size_t>(bytes, 64 * 1024);
+        CUTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&b_->p), cap, hipHostMallocDefault));
+        b_->cap = cap;
+    }
+    *p = b_->p;
+    return CUTE_OK;
+}
+
+HostStage::~HostStage() {
+    if (!b_) return;
+    int dev = -1;
+    bool ok = hipGetDevice(&dev) == hipSuccess;
+    if (ok && b_->dev != dev) {
+        if (b_->done) (void)hipEventDestroy(b_->done);
+        b_->done = nullptr;
+        b_->dev = dev;
+        if (hipEventCreateWithFlags(&b_->done, hipEventDisableTiming) != hipSuccess)
+            b_->done = nullptr;
+    }
+    if (!ok || !b_->done || hipEventRecord(b_->done, s_) != hipSuccess) {
+        // no event to wait on later: wait for the copies now
+        (void)hipStreamSynchronize(s_);
+        if (b_->done) {
+            (void)hipEventDestroy(b_->done);
+            b_->done = nullptr;
+            b_->dev = -1;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g_stage_free.push_back(b_);
+}
+
 }  // namespace cute
 
 using namespace cute;
@@ -136,7 +196,8 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     hipStream_t hs = (hipStream_t)stream;
 
     // ---- device buffers: one block, filled by one copy ------------------------
-    // [T1 | T2 | B1 | B2 | stencil | args | counts, stats[4], head]
+    // [T1 | T2 | B1 | B2 | stencil | args | counts, stats[4], head, tile count,
+    //  tile-slot overflow]
     auto up16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
     const size_t oT1 = 0;
     const size_t oT2 = oT1 + up16(pl.T1.size() * 8);
@@ -145,20 +206,31 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     const size_t oST = oB2 + up16(pl.band2.size() * 8);
     const size_t oAR = oST + up16(geo.stencil.size() * sizeof(int4));
     const size_t oWK = oAR + up16(sizeof(CountArgs));
-    const size_t total = oWK + ((size_t)nbins + 5) * 8;
+    const size_t total = oWK + ((size_t)nbins + 7) * 8;
     TempList tmp(hs);
     unsigned char* blob = nullptr;
     if ((s = tmp.alloc(&blob, total)) != CUTE_OK) return s;
+    // pinned staging: [blob image | argument block | read-back of counts and
+    // statistics]; the lease outlives every copy below (declared after tmp,
+    // released first, which records its event after the copies)
+    const size_t hArgs = up16(total), hBack = hArgs + up16(sizeof(CountArgs));
+    HostStage stage(hs);
+    unsigned char* hb = nullptr;
+    if ((s = stage.get(hBack + ((size_t)nbins + 7) * 8, &hb)) != CUTE_OK) return s;
     // tables and zeroed counts in one copy (the argument block follows later)
-    std::vector<unsigned char> hb(total, 0);
-    memcpy(hb.data() + oT1, pl.T1.data(), pl.T1.size() * 8);
-    memcpy(hb.data() + oT2, pl.T2.data(), pl.T2.size() * 8);
-    memcpy(hb.data() + oB1, pl.band1.data(), pl.band1.size() * 8);
-    memcpy(hb.data() + oB2, pl.band2.data(), pl.band2.size() * 8);
+    memset(hb, 0, total);
+    memcpy(hb + oT1, pl.T1.data(), pl.T1.size() * 8);
+    memcpy(hb + oT2, pl.T2.data(), pl.T2.size() * 8);
+    memcpy(hb + oB1, pl.band1.data(), pl.band1.size() * 8);
+    memcpy(hb + oB2, pl.band2.data(), pl.band2.size() * 8);
     if (!geo.stencil.empty())
-        memcpy(hb.data() + oST, geo.stencil.data(), geo.stencil.size() * sizeof(int4));
-    CUTE_HIP(hipMemcpyAsync(blob, hb.data(), total, hipMemcpyHostToDevice, hs));
+        memcpy(hb + oST, geo.stencil.data(), geo.stencil.size() * sizeof(int4));
+    CUTE_HIP(hipMemcpyAsync(blob, hb, total, hipMemcpyHostToDevice, hs));
     unsigned long long* work = reinterpret_cast<unsigned long long*>(blob + oWK);
+    // the tile count and the slot-overflow flag, when the tiles are built
+    // without a wait
+    uint32_t* ntiles_dev = reinterpret_cast<uint32_t*>(work + nbins + 5);
+    uint32_t* slot_overflow = reinterpret_cast<uint32_t*>(work + nbins + 6);
     CountArgs* dargs = reinterpret_cast<CountArgs*>(blob + oAR);
     if (rad) {
         // redshifts in each grid's sorted order
@@ -186,18 +258,34 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     a.work_head = reinterpret_cast<uint32_t*>(work + nbins + 4);
 
     Tile* tiles = nullptr;
-    uint32_t ntiles = 0;
+    uint32_t ntiles = 0;   // the count, or with dev_count the capacity of tiles
+    bool dev_count = false;
     if (A.n > 0 && B.n > 0) {
         GridHost At = A;
-        if ((s = build_tiles(At, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
         // Too few tiles to give every wave slot of the chip two: cut them
         // shorter (default tile size only; not below 16 points, where the
         // per-tile neighbour walk starts to dominate).
         int ncu = 0;
-        if (A.tile_auto && max_tiles == 0 &&
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
-            const uint32_t want = (uint32_t)ncu * 16u * 2u;
-            while (ntiles < want && At.tile_max > 16) {
+        const bool may_shrink =
+            A.tile_auto && max_tiles == 0 &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
+        const uint64_t want = (uint64_t)ncu * 16u * 2u;
+        // Every tile holds at most tile_max points. When that many tiles
+        // already fill the chip and the host-side bound on their number is
+        // modest, build them into slots without waiting for their count; the
+        // longest-first reordering compacts them and leaves the count on the
+        // device.
+        const uint64_t min_tiles = ((uint64_t)A.n + At.tile_max - 1) / At.tile_max;
+        const uint64_t bound = tile_count_bound(At, geo.max_w);
+        if (max_tiles == 0 && dst != nullptr && a.nst > 0 && (!may_shrink || min_tiles >= want) &&
+            bound <= std::max<uint64_t>(65536, 4 * min_tiles)) {
+            if ((s = build_tiles_nowait(At, geo.max_w, hs, &tiles, &ntiles, slot_overflow)) !=
+                CUTE_OK)
+                return s;
+            dev_count = true;
+        } else {
+            if ((s = build_tiles(At, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
+            while (may_shrink && ntiles < want && At.tile_max > 16) {
                 At.tile_max = std::max(16, At.tile_max / 2);
                 dfree(tiles, hs);
                 tiles = nullptr;
@@ -205,8 +293,8 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
             }
         }
     }
-    if ((s = order_tiles(A, B, dst, a.nst, is_auto, geo.periodic != 0, &tiles, ntiles, hs)) !=
-        CUTE_OK) {
+    if ((s = order_tiles(A, B, dst, a.nst, is_auto, geo.periodic != 0, &tiles, ntiles, hs,
+                         dev_count ? ntiles_dev : nullptr)) != CUTE_OK) {
         dfree(tiles, hs);
         return s;
     }
@@ -233,10 +321,12 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     }
     a.tiles = tiles;
     a.ntiles = ntiles;
+    a.ntiles_dev = dev_count ? ntiles_dev : nullptr;
     a.self = dargs;
     a.wA = A.wt;
     a.wB = B.wt;
-    CUTE_HIP(hipMemcpyAsync(dargs, &a, sizeof(a), hipMemcpyHostToDevice, hs));
+    memcpy(hb + hArgs, &a, sizeof(a));
+    CUTE_HIP(hipMemcpyAsync(dargs, hb + hArgs, sizeof(a), hipMemcpyHostToDevice, hs));
 
     // launch, then the copies, then one wait (the end event is read after it)
     int grid = 0;
@@ -258,20 +348,18 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     }
     timer.stop();
     dfree(tiles, hs);
-    if (counts_on_device) {
+    if (counts_on_device)
         CUTE_HIP(hipMemcpyAsync(counts, work, (size_t)nbins * 8, hipMemcpyDeviceToDevice, hs));
-    } else {
-        CUTE_HIP(hipMemcpyAsync(counts, work, (size_t)nbins * 8, hipMemcpyDeviceToHost, hs));
-    }
-    // the statistics, and with device counts and statistics asked for, a host
-    // copy of the counts for their sum (counts and statistics are adjacent)
-    const bool sum_dev = counts_on_device && st;
-    std::vector<unsigned long long> hw(sum_dev ? (size_t)nbins + 4 : 4, 0ull);
-    const unsigned long long* hst = hw.data() + (sum_dev ? nbins : 0);
-    CUTE_HIP(hipMemcpyAsync(hw.data(), sum_dev ? work : work + nbins, hw.size() * 8,
-                            hipMemcpyDeviceToHost, hs));
+    // one read-back of [counts | statistics, head, tile count] (the counts
+    // only when they go to the host or their sum is asked for)
+    const bool back_counts = !counts_on_device || st;
+    const unsigned long long* hw = reinterpret_cast<const unsigned long long*>(hb + hBack);
+    const unsigned long long* hst = hw + (back_counts ? nbins : 0);
+    CUTE_HIP(hipMemcpyAsync(hb + hBack, back_counts ? work : work + nbins,
+                            ((back_counts ? (size_t)nbins : 0) + 7) * 8, hipMemcpyDeviceToHost, hs));
     CUTE_HIP(hipStreamSynchronize(hs));
     const double ms = ntiles > 0 ? timer.elapsed_ms() : 0.0;
+    if (!counts_on_device) memcpy(counts, hw, (size_t)nbins * 8);
     if (st) {
         st->pair_evals = hst[0];
         st->retests = hst[1];
@@ -279,10 +367,12 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
         st->tiles = hst[3];
         st->ms_count = ms;
         uint64_t tot = 0;
-        for (int k = 0; k < nbins; k++) tot += sum_dev ? (uint64_t)hw[k] : counts[k];
+        for (int k = 0; k < nbins; k++) tot += (uint64_t)hw[k];
         st->pairs_in_range = tot;
     }
-    if (hst[3] != ntiles) return fail(CUTE_E_INTERNAL, "not every tile was processed");
+    if (dev_count && hst[6] != 0) return fail(CUTE_E_INTERNAL, "tile slots overflowed");
+    const uint64_t want_tiles = dev_count ? (uint64_t)hst[5] : (uint64_t)ntiles;
+    if (hst[3] != want_tiles) return fail(CUTE_E_INTERNAL, "not every tile was processed");
     return CUTE_OK;
 }
 

@@ -69,11 +69,12 @@ __global__ __launch_bounds__(256, 4) void k_count(CountArgs P) {
     S.f = S.b + kSpanCap;
     S.n = 0;
 
+    const uint32_t ntiles = P.ntiles_dev ? uni(*P.ntiles_dev) : P.ntiles;
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(P.work_head, 1u);
         t = uni(t);
-        if (t >= P.ntiles) break;
+        if (t >= ntiles) break;
         const cu32p tp = (cu32p)(const void*)P.tiles;
         Tile tl;
         tl.start = uni(tp[4 * t]);
@@ -189,9 +190,11 @@ cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int
 // wrap onto themselves); a cell with more points is split. With a region per
 // point (points sorted by region inside each cell), a tile also ends where
 // the region changes. One thread walks one row; with out == nullptr it only
-// counts the tiles.
+// counts the tiles. Only the first cap tiles are written; the count returned
+// includes any beyond.
 __device__ uint32_t walk_row_tiles(const uint32_t* __restrict__ cstart, const uint16_t* __restrict__ reg,
-                                   int nx, int r, int max_w, uint32_t tmax, Tile* __restrict__ out) {
+                                   int nx, int r, int max_w, uint32_t tmax, Tile* __restrict__ out,
+                                   uint32_t cap = 0xffffffffu) {
     const uint32_t* cs = cstart + (size_t)r * nx;
     uint32_t o = 0, fill = 0;
     int first = -1;
@@ -223,7 +226,7 @@ __device__ uint32_t walk_row_tiles(const uint32_t* __restrict__ cstart, const ui
                 while (run > 0) {
                     if (!open || fill == tmax || c - first + 1 > max_w || rg != cur_rg) {
                         if (open) {
-                            if (out) out[o] = cur;
+                            if (out && o < cap) out[o] = cur;
                             o++;
                         }
                         open = true;
@@ -246,7 +249,7 @@ __device__ uint32_t walk_row_tiles(const uint32_t* __restrict__ cstart, const ui
         }
     }
     if (open) {
-        if (out) out[o] = cur;
+        if (out && o < cap) out[o] = cur;
         o++;
     }
     return o;
@@ -266,10 +269,42 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
                                                      const uint16_t* __restrict__ reg, int nx,
                                                      int nrows, int max_w, uint32_t tmax,
                                                      const uint32_t* __restrict__ toff,
-                                                     Tile* __restrict__ tiles) {
+                                                     Tile* __restrict__ tiles,
+                                                     uint32_t* __restrict__ total) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0 && total != nullptr) *total = toff[nrows];
     if (r >= nrows) return;
     (void)walk_row_tiles(cstart, reg, nx, r, max_w, tmax, tiles + toff[r]);
+}
+
+// Tiles without a count pass. Row r, whose points are [s_r, s_{r+1}), owns
+// the slots from b_r = floor(s_r / tmax) + r (W + 1), W = floor((nx - 1) /
+// max_w), up to b_{r+1}: the rows partition [0, tile_count_bound) exactly, so
+// every slot is written, with a tile or as empty. A row of p points has at
+// most floor(p / tmax) + W + 1 tiles (see tile_count_bound), which is at most
+// b_{r+1} - b_r because floor(s / tmax) + floor(p / tmax) <= floor((s + p) /
+// tmax). The last row also takes any slots left before cap, the length of
+// out, and no row writes at or past cap. A row with more tiles than slots
+// (the bound failing) raises *overflow.
+__global__ __launch_bounds__(256) void k_tiles_sparse(const uint32_t* __restrict__ cstart, int nx,
+                                                      int nrows, int max_w, uint32_t tmax,
+                                                      Tile* __restrict__ out, uint32_t cap,
+                                                      uint32_t* __restrict__ overflow) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const uint64_t W1 = (uint64_t)((uint32_t)(nx - 1) / (uint32_t)max_w) + 1u;
+    const uint32_t p0 = cstart[(size_t)r * nx], p1 = cstart[(size_t)(r + 1) * nx];
+    const uint64_t b0 = (uint64_t)(p0 / tmax) + (uint64_t)r * W1;
+    uint64_t b1 = r + 1 == nrows ? (uint64_t)cap : (uint64_t)(p1 / tmax) + (uint64_t)(r + 1) * W1;
+    if (b1 > cap) {
+        atomicOr(overflow, 1u);
+        b1 = cap;
+    }
+    const uint32_t slots = b0 < b1 ? (uint32_t)(b1 - b0) : 0u;
+    Tile* o = out + b0;
+    const uint32_t k = walk_row_tiles(cstart, nullptr, nx, r, max_w, tmax, o, slots);
+    if (k > slots) atomicOr(overflow, 1u);
+    for (uint32_t i = k; i < slots; i++) o[i] = Tile{0u, 0u, 0u, 0u};
 }
 
 namespace {
@@ -288,8 +323,8 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
                                                    uint32_t* __restrict__ rank,
                                                    uint32_t* __restrict__ hist) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = t < ntiles;
-    const Tile tl = live ? tiles[t] : Tile{0u, 0u, 0u, 0u};
+    const Tile tl = t < ntiles ? tiles[t] : Tile{0u, 0u, 0u, 0u};
+    const bool live = tl.end > tl.start;  // empty slots are not tiles
     const int c0 = (int)(tl.c0c1 & 0xffffu), c1 = (int)(tl.c0c1 >> 16);
     const int cy = (int)(tl.row % (uint32_t)any), cz = (int)(tl.row / (uint32_t)any);
     uint64_t nb = 0, rows = 0;
@@ -347,7 +382,8 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const Tile* __restrict__ t
                                                       const uint32_t* __restrict__ key,
                                                       const uint32_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ hist,
-                                                      Tile* __restrict__ out) {
+                                                      Tile* __restrict__ out,
+                                                      uint32_t* __restrict__ total) {
     __shared__ uint32_t off[kCostBuckets];
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
@@ -355,11 +391,14 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const Tile* __restrict__ t
             off[b] = acc;
             acc += hist[b];
         }
+        if (blockIdx.x == 0 && total != nullptr) *total = acc;
     }
     __syncthreads();
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    out[off[key[t]] + rank[t]] = tiles[t];
+    const Tile tl = tiles[t];
+    if (tl.end == tl.start) return;  // an empty slot
+    out[off[key[t]] + rank[t]] = tl;
 }
 
 }  // namespace
@@ -368,8 +407,10 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const Tile* __restrict__ t
 // waves take the heavy tiles early and the light ones fill the tail.
 cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stencil, int nst,
                         bool is_auto, bool periodic, Tile** tiles, uint32_t ntiles,
-                        hipStream_t s) {
-    if (ntiles < 2 || stencil == nullptr || nst <= 0) return CUTE_OK;
+                        hipStream_t s, uint32_t* total) {
+    if (total != nullptr && (stencil == nullptr || nst <= 0 || ntiles == 0))
+        return fail(CUTE_E_INTERNAL, "tile compaction needs the neighbour rows");
+    if ((total == nullptr && ntiles < 2) || stencil == nullptr || nst <= 0) return CUTE_OK;
     TempList tmp(s);
     uint32_t *key = nullptr, *rank = nullptr, *hist = nullptr;
     Tile* t1 = nullptr;
@@ -377,7 +418,7 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
     if ((st = tmp.alloc(&key, ntiles)) != CUTE_OK) return st;
     if ((st = tmp.alloc(&rank, ntiles)) != CUTE_OK) return st;
     if ((st = tmp.alloc(&hist, kCostBuckets)) != CUTE_OK) return st;
-    CUTE_HIP(hipMemsetAsync(hist, 0, kCostBuckets * sizeof(uint32_t), s));
+    if ((st = zero_u32(hist, kCostBuckets, s)) != CUTE_OK) return st;
     if ((st = dalloc(&t1, ntiles, s)) != CUTE_OK) return st;
     const unsigned nb = (ntiles + 255u) / 256u;
     hipLaunchKernelGGL(k_tile_cost, dim3(nb), dim3(256), 0, s, *tiles, ntiles, B.cstart, A.ny, B.nx,
@@ -385,7 +426,7 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(256), 0, s, *tiles, ntiles, key, rank,
-                           hist, t1);
+                           hist, t1, total);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
@@ -418,7 +459,7 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     if ((st = dalloc(&t, total, s)) != CUTE_OK) return st;
     if (total > 0) {
         hipLaunchKernelGGL(k_tiles_write, dim3(nb), dim3(256), 0, s, g.cstart, reg, g.nx, nrows,
-                           max_w, (uint32_t)g.tile_max, cnt, t);
+                           max_w, (uint32_t)g.tile_max, cnt, t, (uint32_t*)nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             dfree(t, s);
@@ -427,6 +468,39 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
     }
     *tiles = t;
     *ntiles = total;
+    return CUTE_OK;
+}
+
+// In a row, a tile is opened by the row's first point, after a tile of tmax
+// points (at most floor(points / tmax) times) or when the next point lies
+// max_w cells or more past the open tile's first cell (the first cell then
+// advances by at least max_w: at most floor((nx - 1) / max_w) times).
+uint64_t tile_count_bound(const GridHost& g, int max_w) {
+    const uint64_t rows = (uint64_t)g.ny * (uint64_t)g.nz;
+    const uint64_t w = (uint64_t)(max_w < 1 ? 1 : max_w);
+    return (uint64_t)g.n / (uint64_t)g.tile_max + rows * ((uint64_t)(g.nx - 1) / w + 1u);
+}
+
+cute_status build_tiles_nowait(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
+                               uint32_t* cap, uint32_t* overflow) {
+    *tiles = nullptr;
+    *cap = 0;
+    const uint64_t bound = tile_count_bound(g, max_w);
+    if (bound >= (uint64_t(1) << 31)) return fail(CUTE_E_INTERNAL, "tile bound too large");
+    const int nrows = g.ny * g.nz;
+    Tile* t = nullptr;
+    cute_status st = dalloc(&t, (size_t)bound, s);
+    if (st != CUTE_OK) return st;
+    const unsigned nb = (unsigned)((nrows + 255) / 256);
+    hipLaunchKernelGGL(k_tiles_sparse, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows,
+                       max_w < 1 ? 1 : max_w, (uint32_t)g.tile_max, t, (uint32_t)bound, overflow);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        dfree(t, s);
+        return hip_status(e, "tiles launch");
+    }
+    *tiles = t;
+    *cap = (uint32_t)bound;
     return CUTE_OK;
 }
 

@@ -56,6 +56,8 @@ struct CountArgs {
     GridView A, B;
     const Tile* tiles;
     uint32_t ntiles;
+    const uint32_t* ntiles_dev;     // when set, the tile count in device memory (ntiles is
+                                    // then only the capacity of tiles)
     uint32_t* work_head;            // next tile to pop (global counter)
     unsigned long long* counts;     // nbins global uint64 counts
     unsigned long long* stats;      // [0] pair evals, [1] retests, [2] flips, [3] tiles
@@ -241,11 +243,22 @@ cute_status exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, hipStrea
 cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
                         uint32_t* ntiles, const uint16_t* reg = nullptr);
 
+// The same tiles without a wait for their count (no region labels): *tiles
+// holds *cap = tile_count_bound slots, rows in order, with empty tiles
+// (start == end) in the unused slots, for order_tiles to drop. *overflow
+// (device memory) is raised if a row had more tiles than its slots.
+cute_status build_tiles_nowait(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
+                               uint32_t* cap, uint32_t* overflow);
+// upper bound of the number of tiles of g (no region labels)
+uint64_t tile_count_bound(const GridHost& g, int max_w);
+
 // reorder *tiles longest first by estimated cost (needs the precomputed
-// neighbour rows on the device; a no-op without them)
+// neighbour rows on the device; a no-op without them). With total set, empty
+// tiles are dropped and the number kept is written to *total (device
+// memory); the neighbour rows are then required.
 cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stencil, int nst,
                         bool is_auto, bool periodic, Tile** tiles, uint32_t ntiles,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t* total = nullptr);
 
 // persistent count launch; *grid_used receives the number of workgroups
 // out[i] = in[input index of sorted point i] for the n points of g (in:
@@ -266,6 +279,7 @@ cute_status batch_launch(const BatchArgs& ba, int mode, int prec, int est, int g
                          hipStream_t s);
 cute_status mask_bits(const uint8_t* mask, const GridHost& g, uint32_t* bits, hipStream_t s);
 cute_status zero_u64(unsigned long long* p, size_t n, hipStream_t s);
+cute_status zero_u32(uint32_t* p, size_t n, hipStream_t s);
 
 }  // namespace cute
 

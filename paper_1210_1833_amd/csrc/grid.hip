@@ -441,8 +441,7 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
     uint32_t* key = nullptr;  // keys and ranks in one temporary
     if ((st = tmp.alloc(&key, 2 * (size_t)n)) != CUTE_OK) return cleanup(st);
     uint32_t* rank = key + n;
-    if (hipMemsetAsync(g.cstart, 0, (ncells + 1) * sizeof(uint32_t), s) != hipSuccess)
-        return cleanup(fail(CUTE_E_DEVICE, "hipMemsetAsync"));
+    if ((st = zero_u32(g.cstart, (size_t)ncells + 1, s)) != CUTE_OK) return cleanup(st);
     CellGeo cg{(int)g.geom, g.nx, g.ny, g.nz, g.ox, g.oy, g.oz, g.ax, g.ay, g.az, g.L};
     if (n > 0) {
         unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);

@@ -51,6 +51,25 @@ struct TempList {
     }
 };
 
+// Pinned host memory for the small copies of one call, leased from a pool
+// of buffers that are kept for reuse (never freed). The copies stay
+// asynchronous: releasing the lease records an event on the call's stream,
+// and the next lease of the buffer waits for it.
+struct StageBuf;
+class HostStage {
+  public:
+    explicit HostStage(hipStream_t s) : s_(s) {}
+    // a buffer of at least `bytes` (contents undefined)
+    cute_status get(size_t bytes, unsigned char** p);
+    ~HostStage();
+    HostStage(const HostStage&) = delete;
+    HostStage& operator=(const HostStage&) = delete;
+
+  private:
+    hipStream_t s_;
+    StageBuf* b_ = nullptr;
+};
+
 struct EventTimer {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s;

@@ -100,6 +100,32 @@ def test_tile_sizes(tile):
                                                            prec), want)
 
 
+def test_tile_slots_after_pool_reuse():
+    """Tiles built into per-row slots without a host wait: every slot is
+    written, with a tile or as an empty one, also when the memory pool hands
+    back blocks that held the tiles of an earlier, larger count. Tile sizes 3
+    and 7 put most row boundaries inside a tile, where slots stay empty."""
+    big = catalogs.mixed_periodic(60000, 300.0, seed=211)
+    small = catalogs.mixed_periodic(4000, 300.0, seed=212)
+    e = np.linspace(0.0, 30.0, 16)
+    bn = cute.Binning(cute.BIN_MONO, e)
+    want = oracle.count_pairs(small, None, oracle.Binning(oracle.MONO, e, periodic=True, L=300.0),
+                              prune=True)
+    for tile in (3, 7):
+        say("slot reuse: tile %d" % tile)
+        gb = cute.build_grid(big, cute.GEOM_BOX_PERIODIC, box_size=300.0, r_max=30.0,
+                             tile_points=tile)
+        assert cute.count_pairs(gb, None, bn, cute.PREC_FP32_EDGE).sum() > 0
+        gb.close()
+        gs = cute.build_grid(small, cute.GEOM_BOX_PERIODIC, box_size=300.0, r_max=30.0,
+                             tile_points=tile)
+        for prec in EXACT:
+            got, st = cute.count_pairs(gs, None, bn, prec, with_stats=True)
+            np.testing.assert_array_equal(got, want)
+            assert st["pairs_in_range"] == want.sum()
+        gs.close()
+
+
 def _shell_catalog(rmax, seed, n_blobs=300, per=40, spread=0.5):
     """Blobs whose centres sit at separations close to rmax from other blobs
     (just inside, exactly at, just outside), so that most steps of a count lie

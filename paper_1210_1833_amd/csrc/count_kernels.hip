@@ -286,25 +286,69 @@ __global__ __launch_bounds__(256) void k_tiles_write(const uint32_t* __restrict_
 // tmax). The last row also takes any slots left before cap, the length of
 // out, and no row writes at or past cap. A row with more tiles than slots
 // (the bound failing) raises *overflow.
+// One wave per row: the lanes load 64 cell offsets at a time, the walk (the
+// cuts of walk_row_tiles without regions, on wave-uniform values) reads them
+// with readlane, lane 0 writes the tiles and all lanes the empty slots.
 __global__ __launch_bounds__(256) void k_tiles_sparse(const uint32_t* __restrict__ cstart, int nx,
                                                       int nrows, int max_w, uint32_t tmax,
                                                       Tile* __restrict__ out, uint32_t cap,
                                                       uint32_t* __restrict__ overflow) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int r = unii((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     if (r >= nrows) return;
+    const uint32_t* cs = cstart + (size_t)r * nx;
     const uint64_t W1 = (uint64_t)((uint32_t)(nx - 1) / (uint32_t)max_w) + 1u;
-    const uint32_t p0 = cstart[(size_t)r * nx], p1 = cstart[(size_t)(r + 1) * nx];
+    const uint32_t p0 = uni(cs[0]), p1 = uni(cs[nx]);
     const uint64_t b0 = (uint64_t)(p0 / tmax) + (uint64_t)r * W1;
     uint64_t b1 = r + 1 == nrows ? (uint64_t)cap : (uint64_t)(p1 / tmax) + (uint64_t)(r + 1) * W1;
+    bool over = false;
     if (b1 > cap) {
-        atomicOr(overflow, 1u);
+        over = true;
         b1 = cap;
     }
     const uint32_t slots = b0 < b1 ? (uint32_t)(b1 - b0) : 0u;
     Tile* o = out + b0;
-    const uint32_t k = walk_row_tiles(cstart, nullptr, nx, r, max_w, tmax, o, slots);
-    if (k > slots) atomicOr(overflow, 1u);
-    for (uint32_t i = k; i < slots; i++) o[i] = Tile{0u, 0u, 0u, 0u};
+    uint32_t k = 0, fill = 0;
+    int first = -1;
+    bool open = false;
+    Tile cur{0u, 0u, 0u, 0u};
+    for (int cb = 0; cb < nx; cb += 64) {
+        // offsets of cells cb .. cb + 63 in the lanes, of cell cb + 64 beside
+        const uint32_t v = cb + lane <= nx ? cs[cb + lane] : 0u;
+        const uint32_t vn = cb + 64 <= nx ? uni(cs[cb + 64]) : 0u;
+        const int m = nx - cb < 64 ? nx - cb : 64;
+        for (int j = 0; j < m; j++) {
+            const int c = cb + j;
+            uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+            const uint32_t end = j + 1 < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)v, j + 1) : vn;
+            while (pos < end) {
+                if (!open || fill == tmax || c - first + 1 > max_w) {
+                    if (open) {
+                        if (lane == 0 && k < slots) o[k] = cur;
+                        k++;
+                    }
+                    open = true;
+                    fill = 0;
+                    first = c;
+                    cur.start = pos;
+                    cur.end = pos;
+                    cur.row = (uint32_t)r;
+                    cur.c0c1 = (uint32_t)c | ((uint32_t)c << 16);
+                }
+                const uint32_t take = tmax - fill < end - pos ? tmax - fill : end - pos;
+                fill += take;
+                pos += take;
+                cur.end = pos;
+                cur.c0c1 = (cur.c0c1 & 0xffffu) | ((uint32_t)c << 16);
+            }
+        }
+    }
+    if (open) {
+        if (lane == 0 && k < slots) o[k] = cur;
+        k++;
+    }
+    if ((over || k > slots) && lane == 0) atomicOr(overflow, 1u);
+    for (uint32_t i = k + (uint32_t)lane; i < slots; i += 64u) o[i] = Tile{0u, 0u, 0u, 0u};
 }
 
 namespace {
@@ -315,20 +359,33 @@ namespace {
 // neighbour rows (grids of one geometry), so it is integer work.
 constexpr uint32_t kCostBuckets = 256;
 
+constexpr uint32_t kNoTile = 0xffffffffu;  // the key of an empty slot
+
+// One wave per tile slot, the lanes taking the stencil rows; writes the
+// tile's cost bucket to key[t] (kNoTile for an empty slot).
 __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tiles, uint32_t ntiles,
                                                    const uint32_t* __restrict__ cs, int any, int nx,
                                                    int ny, int nz, const int4* __restrict__ st,
                                                    int nst, int periodic, int is_auto,
-                                                   uint32_t* __restrict__ key,
-                                                   uint32_t* __restrict__ rank,
-                                                   uint32_t* __restrict__ hist) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const Tile tl = t < ntiles ? tiles[t] : Tile{0u, 0u, 0u, 0u};
-    const bool live = tl.end > tl.start;  // empty slots are not tiles
+                                                   uint32_t* __restrict__ key) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t t = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (t >= ntiles) return;
+    const cu32p tp = (cu32p)(const void*)tiles;
+    Tile tl;
+    tl.start = uni(tp[4 * t]);
+    tl.end = uni(tp[4 * t + 1]);
+    tl.row = uni(tp[4 * t + 2]);
+    tl.c0c1 = uni(tp[4 * t + 3]);
+    if (tl.end <= tl.start) {  // empty slots are not tiles
+        if (lane == 0) key[t] = kNoTile;
+        return;
+    }
     const int c0 = (int)(tl.c0c1 & 0xffffu), c1 = (int)(tl.c0c1 >> 16);
     const int cy = (int)(tl.row % (uint32_t)any), cz = (int)(tl.row / (uint32_t)any);
-    uint64_t nb = 0, rows = 0;
-    for (int e = 0; live && e < nst; e++) {
+    uint64_t nb = 0;
+    uint32_t rows = 0;
+    for (int e = lane; e < nst; e += 64) {
         const int4 o = st[e];
         int by = cy + o.x, bz = cz + o.y;
         const bool same = is_auto && o.x == 0 && o.y == 0;
@@ -353,14 +410,28 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
         }
         rows++;
     }
-    // bucket on a log scale, 8 per octave, largest cost first (bucket 0);
-    // log2(c) is in [11, 64)
-    const uint64_t c = (uint64_t)(tl.end - tl.start) * nb + 128ull * rows + 2048ull;
-    const float lc = (__builtin_amdgcn_logf((float)c) - 11.0f) * 8.0f;
-    const uint32_t b = kCostBuckets - 1u - (uint32_t)fminf(fmaxf(lc, 0.0f), (float)(kCostBuckets - 1));
-    // (a thread past the end joins the barriers and counts nothing)
-    // rank within the bucket: LDS atomics inside the block, then one global
-    // atomic per (block, bucket) reserves the block's range
+    for (int off = 32; off > 0; off >>= 1) {
+        nb += __shfl_xor(nb, off);
+        rows += __shfl_xor(rows, off);
+    }
+    if (lane == 0) {
+        // bucket on a log scale, 8 per octave, largest cost first (bucket 0);
+        // log2(c) is in [11, 64)
+        const uint64_t c = (uint64_t)(tl.end - tl.start) * nb + 128ull * rows + 2048ull;
+        const float lc = (__builtin_amdgcn_logf((float)c) - 11.0f) * 8.0f;
+        key[t] = kCostBuckets - 1u - (uint32_t)fminf(fmaxf(lc, 0.0f), (float)(kCostBuckets - 1));
+    }
+}
+
+// Rank of each tile within its bucket: LDS atomics inside the block, then one
+// global atomic per (block, bucket) reserves the block's range. (A thread past
+// the end or on an empty slot joins the barriers and counts nothing.)
+__global__ __launch_bounds__(256) void k_tile_rank(const uint32_t* __restrict__ key, uint32_t ntiles,
+                                                   uint32_t* __restrict__ rank,
+                                                   uint32_t* __restrict__ hist) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t b = t < ntiles ? key[t] : kNoTile;
+    const bool live = b != kNoTile;
     __shared__ uint32_t lh[kCostBuckets], lbase[kCostBuckets];
     for (uint32_t i = threadIdx.x; i < kCostBuckets; i += blockDim.x) lh[i] = 0u;
     __syncthreads();
@@ -369,10 +440,7 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
     for (uint32_t i = threadIdx.x; i < kCostBuckets; i += blockDim.x)
         if (lh[i]) lbase[i] = atomicAdd(&hist[i], lh[i]);
     __syncthreads();
-    if (live) {
-        key[t] = b;
-        rank[t] = lbase[b] + lr;
-    }
+    if (live) rank[t] = lbase[b] + lr;
 }
 
 // Scatter the tiles into bucket order: every block scans the bucket counts in
@@ -396,9 +464,9 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const Tile* __restrict__ t
     __syncthreads();
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    if (tl.end == tl.start) return;  // an empty slot
-    out[off[key[t]] + rank[t]] = tl;
+    const uint32_t b = key[t];
+    if (b == kNoTile) return;  // an empty slot
+    out[off[b] + rank[t]] = tiles[t];
 }
 
 }  // namespace
@@ -421,9 +489,14 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
     if ((st = zero_u32(hist, kCostBuckets, s)) != CUTE_OK) return st;
     if ((st = dalloc(&t1, ntiles, s)) != CUTE_OK) return st;
     const unsigned nb = (ntiles + 255u) / 256u;
-    hipLaunchKernelGGL(k_tile_cost, dim3(nb), dim3(256), 0, s, *tiles, ntiles, B.cstart, A.ny, B.nx,
-                       B.ny, B.nz, stencil, nst, periodic ? 1 : 0, is_auto ? 1 : 0, key, rank, hist);
+    hipLaunchKernelGGL(k_tile_cost, dim3((ntiles + 3u) / 4u), dim3(256), 0, s, *tiles, ntiles,
+                       B.cstart, A.ny, B.nx, B.ny, B.nz, stencil, nst, periodic ? 1 : 0,
+                       is_auto ? 1 : 0, key);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_tile_rank, dim3(nb), dim3(256), 0, s, key, ntiles, rank, hist);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(256), 0, s, *tiles, ntiles, key, rank,
                            hist, t1, total);
@@ -491,7 +564,7 @@ cute_status build_tiles_nowait(const GridHost& g, int max_w, hipStream_t s, Tile
     Tile* t = nullptr;
     cute_status st = dalloc(&t, (size_t)bound, s);
     if (st != CUTE_OK) return st;
-    const unsigned nb = (unsigned)((nrows + 255) / 256);
+    const unsigned nb = (unsigned)((nrows + 3) / 4);  // one wave per row
     hipLaunchKernelGGL(k_tiles_sparse, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows,
                        max_w < 1 ? 1 : max_w, (uint32_t)g.tile_max, t, (uint32_t)bound, overflow);
     hipError_t e = hipGetLastError();

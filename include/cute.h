@@ -210,7 +210,9 @@ cute_status cute_pixel_map_read(const cute_grid* g, uint32_t* ids, uint32_t* cou
  * CUTE_E_UNSUPPORTED for SIGMAPI with LOS_Z and MIDPOINT in a periodic box.
  * Pixel maps (cute_build_pixel_map) are counted with weights: see there;
  * CUTE_E_INVALID_ARG for a pixel map against a plain grid, CUTE_E_UNSUPPORTED
- * for a pixel map under a binning other than THETA. */
+ * for a pixel map under a binning other than THETA; CUTE_E_INTERNAL if the
+ * library's own checks on its work list fail (a tile left out).
+ * Waits for stream: counts (host or device) and st are complete on return. */
 cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_binning* bins,
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);

@@ -91,6 +91,11 @@ def _load():
                 [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
                 + [ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
                    ctypes.c_int, ctypes.c_void_p])
+            lib.oracle_count_jackknife.restype = ctypes.c_int
+            lib.oracle_count_jackknife.argtypes = (
+                [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(_Binning), ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p])
             lib.oracle_count_weighted.restype = ctypes.c_int
             lib.oracle_count_weighted.argtypes = (
                 [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
@@ -150,7 +155,8 @@ def count_pairs(a, b, binning: Binning, prune: bool = False, nthreads: int | Non
 
     ``b is None``: autocorrelation of ``a`` (unordered pairs i < j).
     Otherwise: cross-correlation, all pairs (i in a, j in b).
-    ``prune`` uses the exact x-window prune (same counts, fewer pairs visited).
+    ``prune`` uses the exact band-and-window prune (same counts, fewer pairs
+    visited).
     """
     lib = _load()
     if nthreads is None:
@@ -168,6 +174,29 @@ def count_pairs(a, b, binning: Binning, prune: bool = False, nthreads: int | Non
     if rc != 0:
         raise ValueError("oracle_count rejected its arguments (rc=%d)" % rc)
     return out.reshape(binning.shape)
+
+
+def count_jackknife(cat, region, K: int, binning: Binning, nthreads: int | None = None):
+    """Leave-one-region-out autocorrelations: ``(total, jack)`` with ``total``
+    the counts of the whole catalog and ``jack[k]`` those of the catalog
+    without the points whose ``region`` label is k (labels in [0, K))."""
+    lib = _load()
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    x, y, z = _xyz(cat)
+    reg = np.ascontiguousarray(region, dtype=np.int32)
+    if len(reg) != len(x):
+        raise ValueError("one region label per point")
+    cb = binning._c()
+    nbins = lib.oracle_nbins(ctypes.byref(cb))
+    total = np.zeros(nbins, dtype=np.uint64)
+    jack = np.zeros((int(K), nbins), dtype=np.uint64)
+    rc = lib.oracle_count_jackknife(x.ctypes.data, y.ctypes.data, z.ctypes.data, len(x),
+                                    reg.ctypes.data, int(K), ctypes.byref(cb), int(nthreads),
+                                    total.ctypes.data, jack.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_count_jackknife rejected its arguments (rc=%d)" % rc)
+    return total.reshape(binning.shape), jack.reshape((int(K),) + binning.shape)
 
 
 def classify(p, q, binning: Binning) -> int:

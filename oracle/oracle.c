@@ -98,36 +98,43 @@ static void plan_free(or_plan* p) {
 }
 
 /* Minimum image of a coordinate difference in a periodic cube of side L. */
-static double wrap(double d, double L) {
+static inline __attribute__((always_inline)) double wrap(double d, double L) {
     if (d > 0.5 * L) return d - L;
     if (d < -0.5 * L) return d + L;
     return d;
 }
 
-/* Largest k in [0, n-1] with t[k] <= v, for t non-decreasing and t[0] <= v. */
-static int last_le(const double* t, int n, double v) {
-    int lo = 0, hi = n; /* invariant: t[lo] <= v, and hi == n or t[hi] > v */
-    while (hi - lo > 1) {
-        int mid = (lo + hi) / 2;
-        if (t[mid] <= v) lo = mid; else hi = mid;
+/* Largest k in [0, n-1] with t[k] <= v, for t non-decreasing and t[0] <= v.
+ * A binary search with a fixed number of halvings: the answer stays in
+ * [lo, lo + len) and t[lo] <= v holds throughout. */
+static inline __attribute__((always_inline)) int last_le(const double* t, int n, double v) {
+    int lo = 0, len = n;
+    while (len > 1) {
+        int half = len / 2;
+        lo = (t[lo + half] <= v) ? lo + half : lo;
+        len -= half;
     }
     return lo;
 }
 
 /* Largest j in [0, n-1] with num >= fl(t[j] * den), given that it holds at j=0.
- * The predicate is monotone in j because t is non-decreasing. */
-static int last_ratio_ge(const double* t, int n, double num, double den) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) / 2;
-        if (num >= t[mid] * den) lo = mid; else hi = mid;
+ * The predicate is monotone in j because t is non-decreasing and den >= 0
+ * (rounding is monotone), so the same halving search applies. */
+static inline __attribute__((always_inline)) int last_ratio_ge(const double* t, int n, double num,
+                                                                double den) {
+    int lo = 0, len = n;
+    while (len > 1) {
+        int half = len / 2;
+        lo = (num >= t[lo + half] * den) ? lo + half : lo;
+        len -= half;
     }
     return lo;
 }
 
 /* Classify one ordered pair. Returns the flattened bin (i1 * n2 + i2, or i1
- * when there is one dimension) or -1 when the pair is not counted. */
-static int classify(const or_plan* p, double px, double py, double pz,
+ * when there is one dimension) or -1 when the pair is not counted. Inlined
+ * into each loop, which is compiled with and without the FMA instructions. */
+static inline __attribute__((always_inline)) int classify(const or_plan* p, double px, double py, double pz,
                     double qx, double qy, double qz) {
     const or_binning* b = &p->b;
     double dx = px - qx, dy = py - qy, dz = pz - qz;
@@ -218,7 +225,21 @@ double oracle_rmax(const or_binning* b) {
 
 /* ------------------------------------------------------------------------ */
 /* Brute force: every pair, as in the double loop of Sec. 3.1.               */
+/* The inner loop over j is a function of its own, compiled twice (with and  */
+/* without the FMA instruction set, chosen at load time): fma() is correctly */
+/* rounded either way, so both give the same counts; the instruction is only */
+/* faster than the library call.                                             */
 /* ------------------------------------------------------------------------ */
+__attribute__((target_clones("fma", "default"), noinline))
+static void brute_row(const or_plan* p, double px, double py, double pz,
+                      const double* xb, const double* yb, const double* zb,
+                      int64_t j0, int64_t nb, uint64_t* h) {
+    for (int64_t j = j0; j < nb; j++) {
+        int k = classify(p, px, py, pz, xb[j], yb[j], zb[j]);
+        if (k >= 0) h[k]++;
+    }
+}
+
 static void count_brute(const or_plan* p,
                         const double* xa, const double* ya, const double* za, int64_t na,
                         const double* xb, const double* yb, const double* zb, int64_t nb,
@@ -228,13 +249,8 @@ static void count_brute(const or_plan* p,
     {
         uint64_t* h = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
 #pragma omp for schedule(dynamic, 64)
-        for (int64_t i = 0; i < na; i++) {
-            int64_t j0 = is_auto ? i + 1 : 0;
-            for (int64_t j = j0; j < nb; j++) {
-                int k = classify(p, xa[i], ya[i], za[i], xb[j], yb[j], zb[j]);
-                if (k >= 0) h[k]++;
-            }
-        }
+        for (int64_t i = 0; i < na; i++)
+            brute_row(p, xa[i], ya[i], za[i], xb, yb, zb, is_auto ? i + 1 : 0, nb, h);
 #pragma omp critical
         for (int k = 0; k < nbins; k++) out[k] += h[k];
         free(h);
@@ -242,98 +258,266 @@ static void count_brute(const or_plan* p,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Exact 1-D window prune: a pair whose x-separation exceeds the largest     */
-/* countable separation cannot be counted, so only pairs inside an x window  */
-/* are classified. The window carries a 1e-9 relative margin, far above the  */
-/* rounding of the FP64 differences, so no countable pair is skipped.        */
+/* Exact band-and-window prune. Every countable pair has a separation below  */
+/* rmax, so |dx| < rmax and |dy| < rmax (minimum image in a periodic box).   */
+/* The points are grouped into bands of y, each at least w = rmax (1 + 1e-9) */
+/* wide, and sorted by x inside each band; only the pairs in the same or in  */
+/* adjacent bands whose x-separation is below w are classified. Two bands    */
+/* two or more apart are separated by a whole band, i.e. |dy| >= w. The 1e-9 */
+/* margin (and a 1e-6 one on the band width) lies far above the rounding of  */
+/* the FP64 differences and of the band index, so no countable pair is       */
+/* skipped; the tests check the result against the brute-force loop.         */
+/* A periodic box uses cyclic bands when there are at least three, else one  */
+/* band (the x window alone, with its periodic images).                       */
 /* ------------------------------------------------------------------------ */
-typedef struct { double x; int64_t i; } xkey;
+typedef struct { int band; double x; int64_t i; } bkey;
 
-static int cmp_xkey(const void* a, const void* b) {
-    double u = ((const xkey*)a)->x, v = ((const xkey*)b)->x;
-    if (u < v) return -1;
-    if (u > v) return 1;
-    int64_t s = ((const xkey*)a)->i, t = ((const xkey*)b)->i;
-    return (s > t) - (s < t);
+static int cmp_bkey(const void* a, const void* b) {
+    const bkey* u = (const bkey*)a;
+    const bkey* v = (const bkey*)b;
+    if (u->band != v->band) return u->band < v->band ? -1 : 1;
+    if (u->x < v->x) return -1;
+    if (u->x > v->x) return 1;
+    return (u->i > v->i) - (u->i < v->i);
 }
 
-/* first index in sorted keys with x >= v */
-static int64_t lower_bound_x(const xkey* k, int64_t n, double v) {
-    int64_t lo = 0, hi = n;
+typedef struct {
+    int nb;             /* bands                                         */
+    int cyclic;         /* bands wrap (periodic box, nb >= 3)            */
+    double y0, bw;      /* band k holds y0 + k bw <= y < y0 + (k+1) bw     */
+} band_geo;
+
+static int band_of(const band_geo* g, double y) {
+    double q = floor((y - g->y0) / g->bw);
+    if (!(q >= 0.0)) return 0;
+    if (q >= (double)(g->nb - 1)) return g->nb - 1;
+    return (int)q;
+}
+
+/* Catalog B sorted by (band, x): coordinates, input index and the first    */
+/* position of each band.                                                    */
+typedef struct {
+    double *x, *y, *z;
+    int64_t* idx;
+    int64_t* start;     /* nb + 1 */
+} banded;
+
+static int banded_init(banded* s, const band_geo* g, const double* x, const double* y,
+                       const double* z, int64_t n) {
+    memset(s, 0, sizeof(*s));
+    size_t m = (size_t)(n > 0 ? n : 1);
+    bkey* k = (bkey*)malloc(sizeof(bkey) * m);
+    s->x = (double*)malloc(sizeof(double) * m);
+    s->y = (double*)malloc(sizeof(double) * m);
+    s->z = (double*)malloc(sizeof(double) * m);
+    s->idx = (int64_t*)malloc(sizeof(int64_t) * m);
+    s->start = (int64_t*)calloc((size_t)g->nb + 1, sizeof(int64_t));
+    if (!k || !s->x || !s->y || !s->z || !s->idx || !s->start) { free(k); return -1; }
+    for (int64_t j = 0; j < n; j++) { k[j].band = band_of(g, y[j]); k[j].x = x[j]; k[j].i = j; }
+    qsort(k, (size_t)n, sizeof(bkey), cmp_bkey);
+    for (int64_t j = 0; j < n; j++) {
+        int64_t i = k[j].i;
+        s->x[j] = x[i]; s->y[j] = y[i]; s->z[j] = z[i]; s->idx[j] = i;
+        s->start[k[j].band + 1]++;
+    }
+    for (int b = 0; b < g->nb; b++) s->start[b + 1] += s->start[b];
+    free(k);
+    return 0;
+}
+
+static void banded_free(banded* s) {
+    free(s->x); free(s->y); free(s->z); free(s->idx); free(s->start);
+}
+
+/* first position in [lo, hi) of the x-sorted run with x >= v */
+static int64_t lower_x(const double* x, int64_t lo, int64_t hi, double v) {
     while (lo < hi) {
         int64_t mid = lo + (hi - lo) / 2;
-        if (k[mid].x < v) lo = mid + 1; else hi = mid;
+        if (x[mid] < v) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
 
-static void count_window(const or_plan* p,
-                         const double* xa, const double* ya, const double* za, int64_t na,
-                         const double* xb, const double* yb, const double* zb, int64_t nb,
-                         int is_auto, uint64_t* out, int nthreads) {
+/* first position in [lo, hi) with x > v */
+static int64_t upper_x(const double* x, int64_t lo, int64_t hi, double v) {
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (x[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* Jackknife regions (optional): the pair counts of the catalog without     */
+/* region k are the total minus the pairs with at least one point in k, so  */
+/* each counted pair also adds 1 to the histogram of every region it        */
+/* touches (once when both points share the region).                        */
+typedef struct {
+    const int32_t* reg;  /* region of each sorted point, or NULL */
+    uint64_t* touch;     /* K * nbins, this thread's               */
+    int nbins;
+} region_acc;
+
+/* Classify point p against the positions [s, e) of the sorted catalog. */
+/* A pair whose FP64 squared separation (formed as the classification forms  */
+/* it) is at least w^2 is skipped before the classification: a counted pair */
+/* has d2 < rmax^2 (1 + 13 u) < w^2 in every binning (for sigma-pi because   */
+/* sigma^2 + pi^2 = r^2 for any line of sight, up to a few roundings).       */
+__attribute__((target_clones("fma", "default"), noinline))
+static void window_row(const or_plan* p, double px, double py, double pz, int32_t rp,
+                       const banded* B, int64_t s, int64_t e, uint64_t* h, const region_acc* ra) {
+    const or_binning* bn = &p->b;
+    const double w = p->rmax * (1.0 + 1e-9), w2 = w * w;
+    for (int64_t c = s; c < e; c++) {
+        double dx = px - B->x[c], dy = py - B->y[c], dz = pz - B->z[c];
+        if (bn->periodic) {
+            dx = wrap(dx, bn->L);
+            dy = wrap(dy, bn->L);
+            dz = wrap(dz, bn->L);
+        }
+        if (fma(dz, dz, fma(dy, dy, dx * dx)) >= w2) continue;
+        int k = classify(p, px, py, pz, B->x[c], B->y[c], B->z[c]);
+        if (k < 0) continue;
+        h[k]++;
+        if (ra->reg) {
+            int32_t rq = ra->reg[c];
+            ra->touch[(size_t)rp * (size_t)ra->nbins + (size_t)k]++;
+            if (rq != rp) ra->touch[(size_t)rq * (size_t)ra->nbins + (size_t)k]++;
+        }
+    }
+}
+
+/* All partners of p in band b of B within the x window (plus the periodic   */
+/* images of the window); with from >= 0 only positions after from (the     */
+/* autocorrelation inside p's own band, where from is p's position).         */
+static void visit_band(const or_plan* p, double w, double px, double py, double pz, int32_t rp,
+                       const banded* B, int b, int64_t from, uint64_t* h, const region_acc* ra) {
+    const or_binning* bn = &p->b;
+    const double* xs = B->x;
+    int64_t s = B->start[b], e = B->start[b + 1];
+    if (from >= 0) s = from + 1;
+    if (s >= e) return;
+    int64_t lo = from >= 0 ? s : lower_x(xs, s, e, px - w);
+    int64_t hi = lower_x(xs, s, e, px + w);
+    if (hi > lo) window_row(p, px, py, pz, rp, B, lo, hi, h, ra);
+    if (!bn->periodic) return;
+    /* partners near the far face: x_b >= x0 + L - w */
+    int64_t s2 = lower_x(xs, s, e, px + bn->L - w);
+    if (s2 < hi) s2 = hi;
+    if (s2 < e) window_row(p, px, py, pz, rp, B, s2, e, h, ra);
+    if (from < 0) {
+        /* partners near the near face: x_b <= x0 - L + w */
+        int64_t e2 = upper_x(xs, s, e, px - bn->L + w);
+        if (e2 > lo) e2 = lo;
+        if (e2 > s) window_row(p, px, py, pz, rp, B, s, e2, h, ra);
+    }
+}
+
+static int band_geometry(const or_plan* p, const double* ya, int64_t na, const double* yb,
+                         int64_t nb, band_geo* g) {
     const or_binning* b = &p->b;
-    int nbins = oracle_nbins(b);
     double w = p->rmax * (1.0 + 1e-9);
-    xkey* kb = (xkey*)malloc(sizeof(xkey) * (size_t)(nb > 0 ? nb : 1));
-    for (int64_t j = 0; j < nb; j++) { kb[j].x = xb[j]; kb[j].i = j; }
-    qsort(kb, (size_t)nb, sizeof(xkey), cmp_xkey);
-    /* For an autocorrelation the sorted array is walked with position b > a,
-     * which visits each unordered pair once. */
+    g->bw = w * (1.0 + 1e-6);
+    g->cyclic = 0;
+    if (b->periodic) {
+        g->y0 = 0.0;
+        double q = floor(b->L / g->bw);
+        g->nb = q >= 3.0 ? (int)(q < 1048576.0 ? q : 1048576.0) : 1;
+        if (g->nb >= 3) {
+            g->bw = b->L / (double)g->nb;   /* >= the width asked for */
+            g->cyclic = 1;
+        }
+        return 0;
+    }
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = 0; i < na; i++) { if (ya[i] < lo) lo = ya[i]; if (ya[i] > hi) hi = ya[i]; }
+    for (int64_t i = 0; i < nb; i++) { if (yb[i] < lo) lo = yb[i]; if (yb[i] > hi) hi = yb[i]; }
+    if (!(hi >= lo)) { lo = hi = 0.0; }
+    g->y0 = lo;
+    double q = floor((hi - lo) / g->bw) + 1.0;
+    if (q > 1048576.0) { g->bw = (hi - lo) / 1048575.0; q = 1048576.0; }
+    g->nb = (int)q;
+    return 0;
+}
+
+static int count_window(const or_plan* p,
+                        const double* xa, const double* ya, const double* za, int64_t na,
+                        const double* xb, const double* yb, const double* zb, int64_t nb,
+                        int is_auto, uint64_t* out, int nthreads,
+                        const int32_t* region, int nreg, uint64_t* touch_out) {
+    int nbins = oracle_nbins(&p->b);
+    double w = p->rmax * (1.0 + 1e-9);
+    band_geo g;
+    band_geometry(p, ya, na, yb, nb, &g);
+    banded B;
+    if (banded_init(&B, &g, xb, yb, zb, nb) != 0) { banded_free(&B); return -1; }
+    int32_t* sreg = NULL;
+    if (region) {
+        sreg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb > 0 ? nb : 1));
+        if (!sreg) { banded_free(&B); return -1; }
+        for (int64_t j = 0; j < nb; j++) sreg[j] = region[B.idx[j]];
+    }
+    int fail = 0;
 #pragma omp parallel num_threads(nthreads)
     {
         uint64_t* h = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+        region_acc ra = {sreg, NULL, nbins};
+        if (sreg) ra.touch = (uint64_t*)calloc((size_t)nreg * (size_t)nbins, sizeof(uint64_t));
+        if (!h || (sreg && !ra.touch)) {
+#pragma omp atomic write
+            fail = 1;
+        }
 #pragma omp for schedule(dynamic, 64)
-        for (int64_t a = 0; a < na; a++) {
-            double px, py, pz, x0;
-            int64_t lo, hi;
+        for (int64_t a = 0; a < (is_auto ? nb : na); a++) {
+            if (fail) continue;
+            double px, py, pz;
+            int32_t rp = 0;
+            int ba;
             if (is_auto) {
-                int64_t i = kb[a].i;
-                px = xb[i]; py = yb[i]; pz = zb[i]; x0 = kb[a].x;
-                lo = a + 1;
+                px = B.x[a]; py = B.y[a]; pz = B.z[a];
+                rp = sreg ? sreg[a] : 0;
+                ba = band_of(&g, py);
+                /* the own band from the next position on, then the next band */
+                visit_band(p, w, px, py, pz, rp, &B, ba, a, h, &ra);
+                int bn1 = ba + 1;
+                if (bn1 == g.nb && g.cyclic) bn1 = 0;
+                if (bn1 < g.nb && bn1 != ba) visit_band(p, w, px, py, pz, rp, &B, bn1, -1, h, &ra);
             } else {
-                px = xa[a]; py = ya[a]; pz = za[a]; x0 = px;
-                lo = lower_bound_x(kb, nb, x0 - w);
-            }
-            hi = lower_bound_x(kb, nb, x0 + w);
-            /* pieces of the window: [lo, hi) plus periodic images */
-            int64_t seg[3][2];
-            int ns = 0;
-            if (hi > lo) { seg[ns][0] = lo; seg[ns][1] = hi; ns++; }
-            if (b->periodic) {
-                /* partners near the other face: x_b >= x0 + L - w */
-                int64_t s = lower_bound_x(kb, nb, x0 + b->L - w);
-                if (is_auto && s < a + 1) s = a + 1;
-                if (s < hi) s = hi;
-                if (s < nb) { seg[ns][0] = s; seg[ns][1] = nb; ns++; }
-                if (!is_auto) {
-                    /* x_b <= x0 - L + w */
-                    int64_t e = lower_bound_x(kb, nb, x0 - b->L + w);
-                    /* include ties at the bound */
-                    while (e < nb && kb[e].x <= x0 - b->L + w) e++;
-                    if (e > lo) e = lo;
-                    if (e > 0) { seg[ns][0] = 0; seg[ns][1] = e; ns++; }
+                px = xa[a]; py = ya[a]; pz = za[a];
+                ba = band_of(&g, py);
+                int bands[3] = {ba - 1, ba, ba + 1}, nvis = 0;
+                for (int t = 0; t < 3; t++) {
+                    int bb = bands[t];
+                    if (g.cyclic) bb = (bb + g.nb) % g.nb;
+                    if (bb < 0 || bb >= g.nb) continue;
+                    int dup = 0;
+                    for (int u = 0; u < t; u++) if (bands[u] == bb) dup = 1;
+                    bands[t] = bb;
+                    if (dup) continue;
+                    visit_band(p, w, px, py, pz, 0, &B, bb, -1, h, &ra);
+                    nvis++;
                 }
-            }
-            for (int s2 = 0; s2 < ns; s2++) {
-                for (int64_t c = seg[s2][0]; c < seg[s2][1]; c++) {
-                    int64_t j = kb[c].i;
-                    int k = classify(p, px, py, pz, xb[j], yb[j], zb[j]);
-                    if (k >= 0) h[k]++;
-                }
+                (void)nvis;
             }
         }
 #pragma omp critical
-        for (int k = 0; k < nbins; k++) out[k] += h[k];
+        {
+            if (h) for (int k = 0; k < nbins; k++) out[k] += h[k];
+            if (ra.touch)
+                for (size_t k = 0; k < (size_t)nreg * (size_t)nbins; k++) touch_out[k] += ra.touch[k];
+        }
         free(h);
+        free(ra.touch);
     }
-    free(kb);
+    free(sreg);
+    banded_free(&B);
+    return fail ? -1 : 0;
 }
 
 /*
  * Count pairs.
  *  is_auto != 0: pairs i < j of catalog B (A is ignored), the autocorrelation.
  *  is_auto == 0: all pairs (i in A, j in B).
- *  prune   != 0: use the exact x-window prune instead of all pairs.
+ *  prune   != 0: use the exact band-and-window prune instead of all pairs.
  * counts (nbins uint64) is overwritten. Returns 0, or -1 on a bad argument.
  */
 int oracle_count(const double* xa, const double* ya, const double* za, int64_t na,
@@ -350,12 +534,49 @@ int oracle_count(const double* xa, const double* ya, const double* za, int64_t n
     if (b->periodic && !(pl.rmax * (1.0 + 1e-9) < 0.5 * b->L)) { plan_free(&pl); return -1; }
     memset(counts, 0, sizeof(uint64_t) * (size_t)oracle_nbins(b));
     if (is_auto) { xa = xb; ya = yb; za = zb; na = nb; }
+    int rc = 0;
     if (prune)
-        count_window(&pl, xa, ya, za, na, xb, yb, zb, nb, is_auto, counts, nthreads);
+        rc = count_window(&pl, xa, ya, za, na, xb, yb, zb, nb, is_auto, counts, nthreads,
+                          NULL, 0, NULL);
     else
         count_brute(&pl, xa, ya, za, na, xb, yb, zb, nb, is_auto, counts, nthreads);
     plan_free(&pl);
-    return 0;
+    return rc;
+}
+
+/*
+ * Jackknife autocorrelations by regions: for every k in [0, K), the pair
+ * counts of the catalog with the points of region k left out (the counts of
+ * Sec. 2.2 on K sub-catalogs). Each one equals the count of the whole
+ * catalog minus the pairs with at least one point in region k, so one pass
+ * over the pairs (with the exact prune) gives all of them.
+ * region: n labels in [0, K). total: nbins (the whole catalog); jack: K * nbins,
+ * row k = the catalog without region k. Returns 0, or -1 on a bad argument.
+ */
+int oracle_count_jackknife(const double* x, const double* y, const double* z, int64_t n,
+                           const int32_t* region, int K, const or_binning* b, int nthreads,
+                           uint64_t* total, uint64_t* jack) {
+    if (!b || !total || !jack || !region || K < 1 || n < 0 || b->n1 < 1) return -1;
+    if ((b->kind == OR_RMU || b->kind == OR_SIGMAPI) && (b->n2 < 1 || !b->e2)) return -1;
+    if (b->kind == OR_SIGMAPI && b->los != OR_LOS_MID) return -1;
+    if (b->periodic && !(b->L > 0.0)) return -1;
+    for (int64_t i = 0; i < n; i++)
+        if (region[i] < 0 || region[i] >= K) return -1;
+    if (nthreads < 1) nthreads = 1;
+    or_plan pl;
+    if (plan_init(&pl, b) != 0) return -1;
+    if (b->periodic && !(pl.rmax * (1.0 + 1e-9) < 0.5 * b->L)) { plan_free(&pl); return -1; }
+    int nbins = oracle_nbins(b);
+    memset(total, 0, sizeof(uint64_t) * (size_t)nbins);
+    uint64_t* touch = (uint64_t*)calloc((size_t)K * (size_t)nbins, sizeof(uint64_t));
+    if (!touch) { plan_free(&pl); return -1; }
+    int rc = count_window(&pl, x, y, z, n, x, y, z, n, 1, total, nthreads, region, K, touch);
+    for (size_t k = 0; k < (size_t)K; k++)
+        for (size_t q = 0; q < (size_t)nbins; q++)
+            jack[k * (size_t)nbins + q] = total[q] - touch[k * (size_t)nbins + q];
+    free(touch);
+    plan_free(&pl);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

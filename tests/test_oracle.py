@@ -331,3 +331,66 @@ def test_rejects_bad_arguments():
         oracle.count_pairs(a, None, Binning(MONO, [0, 5, 6], periodic=True, L=10.0))
     with pytest.raises(ValueError):   # sigma-pi needs the midpoint line of sight
         oracle.count_pairs(a, None, Binning(SIGMAPI, [0, 1], [0, 1], los=LOS_Z))
+
+
+@pytest.mark.parametrize("L,rmax", [(100.0, 30.0), (100.0, 20.0), (100.0, 12.0), (100.0, 45.0)])
+def test_band_prune_periodic_bands_equal_brute_force(L, rmax):
+    """Periodic boxes cut into 3, 4, 8 or (below three) one band of y: the
+    pruned loop equals the brute-force loop, auto and cross, including pairs
+    across the faces of the box."""
+    a = catalogs.mixed_periodic(1500, L, seed=61)
+    b = catalogs.uniform_box(1200, L, seed=62)
+    bn = Binning(MONO, np.linspace(0, rmax, 11), periodic=True, L=L)
+    bm = Binning(RMU, np.linspace(0, rmax, 6), np.linspace(0, 1, 5), los=LOS_Z, periodic=True, L=L)
+    for binning in (bn, bm):
+        for bb in (None, b):
+            full = oracle.count_pairs(a, bb, binning, prune=False)
+            win = oracle.count_pairs(a, bb, binning, prune=True)
+            np.testing.assert_array_equal(full, win)
+            assert full.sum() > 0
+
+
+@pytest.mark.parametrize("rmax", [3.0, 12.0, 60.0])
+def test_band_prune_many_bands_equal_brute_force(rmax):
+    """Open boxes with many bands of y (60, 17 and 4 bands over the catalog)
+    and a light-cone sigma-pi case: pruned equals brute force."""
+    a, b = catalogs.clustered_box_1e6(n_centres=25, per_blob=60, n_rand=1500, box=200.0)
+    bn = Binning(RMU, np.linspace(0, rmax, 7), np.linspace(0, 1, 6), los=LOS_Z)
+    e = np.linspace(0, rmax, 8)
+    bs = Binning(SIGMAPI, e, e, los=LOS_MID)
+    for binning in (bn, bs):
+        for bb in (None, b):
+            full = oracle.count_pairs(a, bb, binning, prune=False)
+            win = oracle.count_pairs(a, bb, binning, prune=True)
+            np.testing.assert_array_equal(full, win)
+            assert full.sum() > 0
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_jackknife_equals_counts_of_subcatalogs(periodic):
+    """Each leave-one-region-out row equals the plain brute-force count of
+    the catalog without that region; the total equals the whole catalog's."""
+    L = 100.0
+    if periodic:
+        cat = catalogs.mixed_periodic(1400, L, seed=71)
+        bins = [Binning(MONO, np.linspace(0, 25, 9), periodic=True, L=L),
+                Binning(RMU, np.linspace(0, 30, 7), np.linspace(0, 1, 6), los=LOS_Z,
+                        periodic=True, L=L)]
+        # 3 x 3 columns in (x, y) plus one region of scattered points
+        reg = (np.minimum((cat.y * 3 / L).astype(int), 2) * 3
+               + np.minimum((cat.x * 3 / L).astype(int), 2)).astype(np.int32)
+        reg[::97] = 9
+        K = 10
+    else:
+        cat, _ = catalogs.clustered_box_1e6(n_centres=20, per_blob=60, n_rand=10, box=150.0)
+        bins = [Binning(MONO, np.linspace(0, 20, 9)),
+                Binning(SIGMAPI, np.linspace(0, 15, 6), np.linspace(0, 15, 6), los=LOS_MID)]
+        reg = (np.arange(len(cat)) % 5).astype(np.int32)
+        K = 6   # region 5 is empty: its row equals the total
+    for bn in bins:
+        total, jack = oracle.count_jackknife(cat, reg, K, bn)
+        np.testing.assert_array_equal(total, oracle.count_pairs(cat, None, bn))
+        for k in range(K):
+            sub = cat.subset(np.nonzero(reg != k)[0])
+            np.testing.assert_array_equal(jack[k], oracle.count_pairs(sub, None, bn),
+                                          err_msg="region %d" % k)

@@ -217,6 +217,31 @@ cute_status cute_count_pairs(const cute_grid* a, const cute_grid* b, const cute_
                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                              cute_count_stats* st, void* stream);
 
+/* ---- Counting without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * count as cute_count_pairs (same arguments, counts, statistics and errors,
+ * and it also waits for its stream), with every device temporary of the call
+ * (threshold and band tables, kernel arguments, counters, the home tiles and
+ * their ordering) in one fixed scratch array of CUTE_NOALLOC_SCRATCH_BYTES
+ * per GPU, which the library holds from the first call on that GPU until the
+ * process ends. The call allocates no device or pinned host memory: its few
+ * host copies go through pageable memory. The home tiles are always built
+ * without a host wait and never cut shorter for small counts.
+ * Every call on one GPU uses the same array and leaves the last call's
+ * contents there; each call clears the counters it needs before its kernels
+ * run. Calls that overlap on one GPU (two host threads or two streams) race
+ * on the array: the caller must serialise them.
+ * Errors: those of cute_count_pairs; CUTE_E_INVALID_ARG, before any work is
+ * enqueued, when the count's temporaries exceed the array (about 64 bytes
+ * per home-tile slot of grid a plus the tables: a 2e7-point grid of 64-point
+ * tiles fits). */
+#define CUTE_NOALLOC_SCRATCH_BYTES (32u << 20)
+cute_status cute_count_pairs_noalloc(const cute_grid* a, const cute_grid* b,
+                                     const cute_binning* bins, cute_precision prec,
+                                     uint64_t* counts, int32_t counts_on_device,
+                                     cute_count_stats* st, void* stream);
+
 /* Radial correlation counts (Sec. 2.1, the radial 2PCF; Sec. 3.4): the pairs
  * of objects aligned with the line of sight, i.e. subtending an angle below
  * the aperture, binned by the difference of their redshifts.

@@ -27,6 +27,7 @@ EST_NATURAL, EST_LS, EST_BOX = range(3)
 BATCH_GRAPH, BATCH_EAGER = range(2)
 
 EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_count_pairs",
+            "cute_count_pairs_noalloc",
             "cute_tune_grid", "cute_batch_create", "cute_batch_run", "cute_batch_counts", "cute_batch_layout",
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched", "cute_count_jackknife",
             "cute_count_jackknife_cross",
@@ -100,6 +101,8 @@ def load():
     lib.cute_count_pairs.restype = ctypes.c_int
     lib.cute_count_pairs.argtypes = [vp, vp, ctypes.POINTER(CBinning), ctypes.c_int, vp,
                                      ctypes.c_int32, ctypes.POINTER(CountStats), vp]
+    lib.cute_count_pairs_noalloc.restype = ctypes.c_int
+    lib.cute_count_pairs_noalloc.argtypes = lib.cute_count_pairs.argtypes
     lib.cute_tune_grid.restype = ctypes.c_int
     lib.cute_tune_grid.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(GridParams),
                                    ctypes.POINTER(CBinning), ctypes.c_int, ctypes.c_int32, dp,
@@ -424,6 +427,31 @@ def count_pairs(a: Grid, b: Grid | None, binning: Binning, prec: int = PREC_FP32
     rc = lib.cute_count_pairs(a.handle, None if b is None else b.handle, ctypes.byref(cb),
                               int(prec), ptr, on_dev, ctypes.byref(st), _stream_handle(stream))
     _check(rc)
+    res = counts.reshape(binning.shape) if out is None else counts
+    return (res, st.as_dict()) if with_stats else res
+
+
+# bytes of the per-GPU scratch array of count_pairs_noalloc (cute.h)
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def count_pairs_noalloc(a: Grid, b: Grid | None, binning: Binning, prec: int = PREC_FP32_EDGE,
+                        out=None, stream=None, with_stats: bool = False):
+    """cute_count_pairs_noalloc: the count of ``count_pairs`` with every
+    device temporary in the library's fixed per-GPU scratch array (no device
+    allocation). Same arguments and results as ``count_pairs``."""
+    lib = load()
+    cb = binning.c()
+    st = CountStats()
+    if out is None:
+        counts = np.zeros(binning.nbins, dtype=np.uint64)
+        ptr, on_dev = counts.ctypes.data, 0
+    else:
+        counts = out
+        ptr, on_dev = out.data_ptr(), 1
+    _check(lib.cute_count_pairs_noalloc(a.handle, None if b is None else b.handle,
+                                        ctypes.byref(cb), int(prec), ptr, on_dev,
+                                        ctypes.byref(st), _stream_handle(stream)))
     res = counts.reshape(binning.shape) if out is None else counts
     return (res, st.as_dict()) if with_stats else res
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["grid.hip", "count_kernels.hip", "batch_kernels.hip", "plan.hip", "capi.hip", "batch.hip", "jackknife.hip", "pixmap.hip", "radial.hip"]
+SOURCES = ["grid.hip", "count_kernels.hip", "batch_kernels.hip", "plan.hip", "capi.hip", "batch.hip", "jackknife.hip", "pixmap.hip", "radial.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "libcute.so")
 BUILD = os.path.join(HERE, "_build")
 

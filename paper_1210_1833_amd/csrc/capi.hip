@@ -49,6 +49,12 @@ cute_status ensure_device_ready(int* device) {
     return CUTE_OK;
 }
 
+cute_status DevArena::scratch_full(size_t need) const {
+    return fail(CUTE_E_INVALID_ARG, "scratch area full: " + std::to_string(need) + " more bytes needed, " +
+                                        std::to_string(cap_ - used_) + " of " + std::to_string(cap_) +
+                                        " left");
+}
+
 struct StageBuf {
     unsigned char* p = nullptr;
     size_t cap = 0;
@@ -143,10 +149,15 @@ struct RadialSpec {
 
 // One pair count; with max_tiles > 0 only an evenly spread sample of about
 // max_tiles home tiles is counted (the tuner's sample).
+// With fixed set, every device temporary is a slice of the caller's fixed
+// area (nothing is allocated or freed, no pinned staging, no new events),
+// the tiles are always built without a host wait, and a count whose
+// temporaries would not fit is rejected before any work is enqueued.
 cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binning* bins,
                        cute_precision prec, uint64_t* counts, int32_t counts_on_device,
                        cute_count_stats* st, void* stream, uint32_t max_tiles,
-                       double* sampled_share = nullptr, const RadialSpec* rad = nullptr) {
+                       double* sampled_share = nullptr, const RadialSpec* rad = nullptr,
+                       const FixedArea* fixed = nullptr) {
     if (!ga) return fail(CUTE_E_INVALID_ARG, "grid a is NULL");
     if (!counts) return fail(CUTE_E_INVALID_ARG, "counts is NULL");
     cute_status s = validate_binning(bins);
@@ -207,16 +218,40 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     const size_t oAR = oST + up16(geo.stencil.size() * sizeof(int4));
     const size_t oWK = oAR + up16(sizeof(CountArgs));
     const size_t total = oWK + ((size_t)nbins + 7) * 8;
-    TempList tmp(hs);
+    if (fixed != nullptr) {
+        if (rad != nullptr || max_tiles > 0)
+            return fail(CUTE_E_INTERNAL, "fixed scratch serves plain counts only");
+        // every temporary of the count, with the slot bound of its tiles
+        const uint64_t bound = A.n > 0 && B.n > 0 ? tile_count_bound(A, geo.max_w) : 0;
+        const size_t need = DevArena::cost<unsigned char>(total) +
+                            2 * DevArena::cost<Tile>((size_t)bound) +
+                            2 * DevArena::cost<uint32_t>((size_t)bound) +
+                            DevArena::cost<uint32_t>(256);
+        if (need > fixed->cap)
+            return fail(CUTE_E_INVALID_ARG,
+                        "this count needs " + std::to_string(need) + " bytes of scratch, more than "
+                        "the " + std::to_string(fixed->cap) + " the no-allocation entry point holds");
+    }
+    DevArena mem_fixed(hs, fixed ? fixed->base : nullptr, fixed ? fixed->cap : 0);
+    DevArena mem_pool(hs);
+    DevArena& tmp = fixed ? mem_fixed : mem_pool;
     unsigned char* blob = nullptr;
-    if ((s = tmp.alloc(&blob, total)) != CUTE_OK) return s;
+    if ((s = tmp.get(&blob, total)) != CUTE_OK) return s;
     // pinned staging: [blob image | argument block | read-back of counts and
     // statistics]; the lease outlives every copy below (declared after tmp,
     // released first, which records its event after the copies)
     const size_t hArgs = up16(total), hBack = hArgs + up16(sizeof(CountArgs));
     HostStage stage(hs);
+    std::vector<unsigned char> pageable;
     unsigned char* hb = nullptr;
-    if ((s = stage.get(hBack + ((size_t)nbins + 7) * 8, &hb)) != CUTE_OK) return s;
+    const size_t hbytes = hBack + ((size_t)nbins + 7) * 8;
+    if (fixed) {
+        // pageable host memory: no pinned allocation (the copies then wait)
+        pageable.resize(hbytes);
+        hb = pageable.data();
+    } else if ((s = stage.get(hbytes, &hb)) != CUTE_OK) {
+        return s;
+    }
     // tables and zeroed counts in one copy (the argument block follows later)
     memset(hb, 0, total);
     memcpy(hb + oT1, pl.T1.data(), pl.T1.size() * 8);
@@ -235,12 +270,12 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     if (rad) {
         // redshifts in each grid's sorted order
         double *rsa = nullptr, *rsb = nullptr;
-        if ((s = tmp.alloc(&rsa, (size_t)A.n)) != CUTE_OK) return s;
+        if ((s = tmp.get(&rsa, (size_t)A.n)) != CUTE_OK) return s;
         if ((s = gather_values(A, rad->ra, rad->on_device != 0, rsa, hs)) != CUTE_OK) return s;
         if (is_auto) {
             rsb = rsa;
         } else {
-            if ((s = tmp.alloc(&rsb, (size_t)B.n)) != CUTE_OK) return s;
+            if ((s = tmp.get(&rsb, (size_t)B.n)) != CUTE_OK) return s;
             if ((s = gather_values(B, rad->rb, rad->on_device != 0, rsb, hs)) != CUTE_OK) return s;
         }
         a.rA = rsa;
@@ -260,7 +295,19 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     Tile* tiles = nullptr;
     uint32_t ntiles = 0;   // the count, or with dev_count the capacity of tiles
     bool dev_count = false;
-    if (A.n > 0 && B.n > 0) {
+    // tiles from the fixed area are never freed
+    auto drop_tiles = [&]() {
+        if (!fixed) dfree(tiles, hs);
+        tiles = nullptr;
+    };
+    if (fixed && A.n > 0 && B.n > 0) {
+        // slots without a host wait, compacted on the device (longest first
+        // when the neighbour rows are tabulated)
+        if ((s = build_tiles_nowait(A, geo.max_w, hs, &tiles, &ntiles, slot_overflow, &tmp)) !=
+            CUTE_OK)
+            return s;
+        dev_count = true;
+    } else if (A.n > 0 && B.n > 0) {
         GridHost At = A;
         // Too few tiles to give every wave slot of the chip two: cut them
         // shorter (default tile size only; not below 16 points, where the
@@ -287,15 +334,14 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
             if ((s = build_tiles(At, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
             while (may_shrink && ntiles < want && At.tile_max > 16) {
                 At.tile_max = std::max(16, At.tile_max / 2);
-                dfree(tiles, hs);
-                tiles = nullptr;
+                drop_tiles();
                 if ((s = build_tiles(At, geo.max_w, hs, &tiles, &ntiles)) != CUTE_OK) return s;
             }
         }
     }
     if ((s = order_tiles(A, B, dst, a.nst, is_auto, geo.periodic != 0, &tiles, ntiles, hs,
-                         dev_count ? ntiles_dev : nullptr)) != CUTE_OK) {
-        dfree(tiles, hs);
+                         dev_count ? ntiles_dev : nullptr, fixed ? &tmp : nullptr)) != CUTE_OK) {
+        drop_tiles();
         return s;
     }
     const uint32_t tile_stride = max_tiles > 0 ? (ntiles + max_tiles - 1) / max_tiles : 1;
@@ -305,7 +351,7 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
         hipError_t e = hipMemcpyAsync(h.data(), tiles, ntiles * sizeof(Tile), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
         if (e != hipSuccess) {
-            dfree(tiles, hs);
+            drop_tiles();
             return hip_status(e, "tile sample");
         }
         uint32_t k = 0;
@@ -315,7 +361,7 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
         e = hipMemcpyAsync(tiles, h.data(), ntiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
         if (e != hipSuccess) {
-            dfree(tiles, hs);
+            drop_tiles();
             return hip_status(e, "tile sample");
         }
     }
@@ -330,11 +376,11 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
 
     // launch, then the copies, then one wait (the end event is read after it)
     int grid = 0;
-    EventTimer timer(hs);
+    EventTimer timer(hs, fixed ? fixed->events : nullptr);
     if (ntiles > 0) {
         s = launch_count(a, pl.mode, (int)prec, pl.est, kWgWaves, pl.lds, hs, &grid);
         if (s != CUTE_OK) {
-            dfree(tiles, hs);
+            drop_tiles();
             return s;
         }
     }
@@ -342,12 +388,12 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     // starts at zero
     if (weighted && is_auto && bins->edges1[0] == 0.0 && sampled_share == nullptr) {
         if ((s = add_pixel_self_pairs(A, work, hs)) != CUTE_OK) {
-            dfree(tiles, hs);
+            drop_tiles();
             return s;
         }
     }
     timer.stop();
-    dfree(tiles, hs);
+    drop_tiles();
     if (counts_on_device)
         CUTE_HIP(hipMemcpyAsync(counts, work, (size_t)nbins * 8, hipMemcpyDeviceToDevice, hs));
     // one read-back of [counts | statistics, head, tile count] (the counts
@@ -377,6 +423,15 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
 }
 
 }  // namespace
+
+cute_status cute::count_pairs_fixed(const cute_grid* a, const cute_grid* b,
+                                    const cute_binning* bins, cute_precision prec,
+                                    uint64_t* counts, int32_t counts_on_device,
+                                    cute_count_stats* st, void* stream, const FixedArea* fixed) {
+    if (!fixed || !fixed->base) return fail(CUTE_E_INTERNAL, "no fixed scratch area");
+    return count_impl(a, b, bins, prec, counts, counts_on_device, st, stream, 0, nullptr, nullptr,
+                      fixed);
+}
 
 extern "C" cute_status cute_count_pairs(const cute_grid* ga, const cute_grid* gb,
                                         const cute_binning* bins, cute_precision prec,

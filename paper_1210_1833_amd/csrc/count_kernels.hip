@@ -423,6 +423,16 @@ __global__ __launch_bounds__(256) void k_tile_cost(const Tile* __restrict__ tile
     }
 }
 
+// Compaction without a cost estimate (grids without precomputed neighbour
+// rows): every tile gets bucket 0, an empty slot kNoTile.
+__global__ __launch_bounds__(256) void k_tile_live(const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                   uint32_t* __restrict__ key) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    key[t] = tl.end > tl.start ? 0u : kNoTile;
+}
+
 // Rank of each tile within its bucket: LDS atomics inside the block, then one
 // global atomic per (block, bucket) reserves the block's range. (A thread past
 // the end or on an empty slot joins the barriers and counts nothing.)
@@ -472,26 +482,39 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const Tile* __restrict__ t
 }  // namespace
 
 // Reorder tiles longest first (estimated cost, descending): the persistent
-// waves take the heavy tiles early and the light ones fill the tail.
+// waves take the heavy tiles early and the light ones fill the tail. Without
+// neighbour rows the tiles keep their order, unless total is set: then the
+// empty slots are only dropped (tiles in no particular order).
 cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stencil, int nst,
                         bool is_auto, bool periodic, Tile** tiles, uint32_t ntiles,
-                        hipStream_t s, uint32_t* total) {
-    if (total != nullptr && (stencil == nullptr || nst <= 0 || ntiles == 0))
-        return fail(CUTE_E_INTERNAL, "tile compaction needs the neighbour rows");
-    if ((total == nullptr && ntiles < 2) || stencil == nullptr || nst <= 0) return CUTE_OK;
-    TempList tmp(s);
+                        hipStream_t s, uint32_t* total, DevArena* ar) {
+    const bool rows = stencil != nullptr && nst > 0;
+    if (total != nullptr && ntiles == 0) return fail(CUTE_E_INTERNAL, "tile compaction without tiles");
+    if (total == nullptr && (ntiles < 2 || !rows)) return CUTE_OK;
+    DevArena pool(s);
+    DevArena& mem = ar != nullptr ? *ar : pool;
     uint32_t *key = nullptr, *rank = nullptr, *hist = nullptr;
     Tile* t1 = nullptr;
     cute_status st;
-    if ((st = tmp.alloc(&key, ntiles)) != CUTE_OK) return st;
-    if ((st = tmp.alloc(&rank, ntiles)) != CUTE_OK) return st;
-    if ((st = tmp.alloc(&hist, kCostBuckets)) != CUTE_OK) return st;
+    if ((st = mem.get(&key, ntiles)) != CUTE_OK) return st;
+    if ((st = mem.get(&rank, ntiles)) != CUTE_OK) return st;
+    if ((st = mem.get(&hist, kCostBuckets)) != CUTE_OK) return st;
     if ((st = zero_u32(hist, kCostBuckets, s)) != CUTE_OK) return st;
-    if ((st = dalloc(&t1, ntiles, s)) != CUTE_OK) return st;
+    // the reordered list outlives this call: from the caller's arena, or its
+    // own pool allocation that replaces (and frees) the input list
+    if (ar != nullptr) {
+        if ((st = ar->get(&t1, ntiles)) != CUTE_OK) return st;
+    } else if ((st = dalloc(&t1, ntiles, s)) != CUTE_OK) {
+        return st;
+    }
     const unsigned nb = (ntiles + 255u) / 256u;
-    hipLaunchKernelGGL(k_tile_cost, dim3((ntiles + 3u) / 4u), dim3(256), 0, s, *tiles, ntiles,
-                       B.cstart, A.ny, B.nx, B.ny, B.nz, stencil, nst, periodic ? 1 : 0,
-                       is_auto ? 1 : 0, key);
+    if (rows) {
+        hipLaunchKernelGGL(k_tile_cost, dim3((ntiles + 3u) / 4u), dim3(256), 0, s, *tiles, ntiles,
+                           B.cstart, A.ny, B.nx, B.ny, B.nz, stencil, nst, periodic ? 1 : 0,
+                           is_auto ? 1 : 0, key);
+    } else {
+        hipLaunchKernelGGL(k_tile_live, dim3(nb), dim3(256), 0, s, *tiles, ntiles, key);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_tile_rank, dim3(nb), dim3(256), 0, s, key, ntiles, rank, hist);
@@ -503,10 +526,10 @@ cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stenci
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
-        dfree(t1, s);
+        if (ar == nullptr) dfree(t1, s);
         return hip_status(e, "tile order");
     }
-    dfree(*tiles, s);
+    if (ar == nullptr) dfree(*tiles, s);
     *tiles = t1;
     return CUTE_OK;
 }
@@ -555,21 +578,21 @@ uint64_t tile_count_bound(const GridHost& g, int max_w) {
 }
 
 cute_status build_tiles_nowait(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
-                               uint32_t* cap, uint32_t* overflow) {
+                               uint32_t* cap, uint32_t* overflow, DevArena* ar) {
     *tiles = nullptr;
     *cap = 0;
     const uint64_t bound = tile_count_bound(g, max_w);
     if (bound >= (uint64_t(1) << 31)) return fail(CUTE_E_INTERNAL, "tile bound too large");
     const int nrows = g.ny * g.nz;
     Tile* t = nullptr;
-    cute_status st = dalloc(&t, (size_t)bound, s);
+    cute_status st = ar != nullptr ? ar->get(&t, (size_t)bound) : dalloc(&t, (size_t)bound, s);
     if (st != CUTE_OK) return st;
     const unsigned nb = (unsigned)((nrows + 3) / 4);  // one wave per row
     hipLaunchKernelGGL(k_tiles_sparse, dim3(nb), dim3(256), 0, s, g.cstart, g.nx, nrows,
                        max_w < 1 ? 1 : max_w, (uint32_t)g.tile_max, t, (uint32_t)bound, overflow);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
-        dfree(t, s);
+        if (ar == nullptr) dfree(t, s);
         return hip_status(e, "tiles launch");
     }
     *tiles = t;

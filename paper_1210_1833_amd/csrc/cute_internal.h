@@ -247,18 +247,21 @@ cute_status build_tiles(const GridHost& g, int max_w, hipStream_t s, Tile** tile
 // holds *cap = tile_count_bound slots, rows in order, with empty tiles
 // (start == end) in the unused slots, for order_tiles to drop. *overflow
 // (device memory) is raised if a row had more tiles than its slots.
+class DevArena;
 cute_status build_tiles_nowait(const GridHost& g, int max_w, hipStream_t s, Tile** tiles,
-                               uint32_t* cap, uint32_t* overflow);
+                               uint32_t* cap, uint32_t* overflow, DevArena* ar = nullptr);
 // upper bound of the number of tiles of g (no region labels)
 uint64_t tile_count_bound(const GridHost& g, int max_w);
 
 // reorder *tiles longest first by estimated cost (needs the precomputed
 // neighbour rows on the device; a no-op without them). With total set, empty
 // tiles are dropped and the number kept is written to *total (device
-// memory); the neighbour rows are then required.
+// memory); without neighbour rows the kept tiles are then in no particular
+// order. With ar, the temporaries and the new list come from the arena and
+// the old list is not freed; otherwise the old list is freed and replaced.
 cute_status order_tiles(const GridHost& A, const GridHost& B, const int4* stencil, int nst,
                         bool is_auto, bool periodic, Tile** tiles, uint32_t ntiles,
-                        hipStream_t s, uint32_t* total = nullptr);
+                        hipStream_t s, uint32_t* total = nullptr, DevArena* ar = nullptr);
 
 // persistent count launch; *grid_used receives the number of workgroups
 // out[i] = in[input index of sorted point i] for the n points of g (in:
@@ -268,6 +271,20 @@ cute_status gather_values(const GridHost& g, const double* in, bool on_device, d
 
 // Add the pairs of objects that share a pixel of a pixel map to *bin.
 cute_status add_pixel_self_pairs(const GridHost& g, unsigned long long* bin, hipStream_t s);
+
+// A caller-provided device area for every temporary of a count, and two
+// timing events made beforehand (the no-allocation entry point).
+struct FixedArea {
+    unsigned char* base;
+    size_t cap;
+    hipEvent_t events[2];
+};
+
+// The pair count of cute_count_pairs with all its device temporaries in
+// *fixed (see there); counts and statistics as cute_count_pairs.
+cute_status count_pairs_fixed(const cute_grid* a, const cute_grid* b, const cute_binning* bins,
+                              cute_precision prec, uint64_t* counts, int32_t counts_on_device,
+                              cute_count_stats* st, void* stream, const FixedArea* fixed);
 
 cute_status launch_count(const CountArgs& args, int mode, int prec, int est, int wg_waves,
                          size_t lds_bytes, hipStream_t stream, int* grid_used);

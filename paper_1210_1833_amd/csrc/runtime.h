@@ -51,6 +51,49 @@ struct TempList {
     }
 };
 
+// Device memory for the temporaries of one call. By default each piece is a
+// stream-ordered pool allocation, freed (in stream order) with the arena.
+// Given a fixed area, the pieces are consecutive 256-byte-aligned slices of
+// it and nothing is allocated or freed; a request beyond the area fails.
+class DevArena {
+  public:
+    explicit DevArena(hipStream_t s) : s_(s) {}
+    DevArena(hipStream_t s, unsigned char* base, size_t cap) : s_(s), base_(base), cap_(cap) {}
+    bool fixed() const { return base_ != nullptr; }
+    size_t capacity() const { return cap_; }
+    // bytes a fixed area spends on `count` elements of T (with alignment)
+    template <typename T>
+    static size_t cost(size_t count) {
+        return ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
+    }
+    template <typename T>
+    cute_status get(T** p, size_t count) {
+        *p = nullptr;
+        if (!fixed()) {
+            cute_status st = dalloc(p, count, s_);
+            if (st == CUTE_OK) owned_.push_back(*p);
+            return st;
+        }
+        const size_t need = cost<T>(count);
+        if (need > cap_ - used_) return scratch_full(need);
+        *p = reinterpret_cast<T*>(base_ + used_);
+        used_ += need;
+        return CUTE_OK;
+    }
+    ~DevArena() {
+        for (void* q : owned_) dfree(q, s_);
+    }
+    DevArena(const DevArena&) = delete;
+    DevArena& operator=(const DevArena&) = delete;
+
+  private:
+    cute_status scratch_full(size_t need) const;
+    hipStream_t s_;
+    unsigned char* base_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
+    std::vector<void*> owned_;
+};
+
 // Pinned host memory for the small copies of one call, leased from a pool
 // of buffers that are kept for reuse (never freed). The copies stay
 // asynchronous: releasing the lease records an event on the call's stream,
@@ -73,11 +116,27 @@ class HostStage {
 struct EventTimer {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s;
+    bool own = true;
     explicit EventTimer(hipStream_t st) : s(st) {
         if (hipEventCreate(&a) != hipSuccess) a = nullptr;
         if (hipEventCreate(&b) != hipSuccess) b = nullptr;
         if (a) (void)hipEventRecord(a, s);
     }
+    // borrowed: two events made beforehand and kept by the caller (none
+    // created here); nullptr: two new events, as above
+    EventTimer(hipStream_t st, const hipEvent_t* borrowed) : s(st) {
+        if (borrowed) {
+            a = borrowed[0];
+            b = borrowed[1];
+            own = false;
+        } else {
+            if (hipEventCreate(&a) != hipSuccess) a = nullptr;
+            if (hipEventCreate(&b) != hipSuccess) b = nullptr;
+        }
+        if (a) (void)hipEventRecord(a, s);
+    }
+    EventTimer(const EventTimer&) = delete;
+    EventTimer& operator=(const EventTimer&) = delete;
     // record the end (no wait)
     void stop() {
         if (a && b) (void)hipEventRecord(b, s);
@@ -95,6 +154,7 @@ struct EventTimer {
         return elapsed_ms();
     }
     ~EventTimer() {
+        if (!own) return;
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
     }

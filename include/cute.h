@@ -408,7 +408,9 @@ cute_status cute_count_jackknife_cross(const cute_grid* a, const int32_t* region
  * volume box_size^3, expected count N(N-1)/2 * V_shell / L^3 with the exact
  * shell volume). nd, nr >= 2. A bin whose denominator is 0 gives NaN.
  * NATURAL and LS evaluate their numerator and denominator exactly in 128-bit
- * integers and divide once. */
+ * integers and divide once; for that they need nd, nr < 2^31 and every count
+ * at most the pairs it can hold (DD <= nd(nd-1)/2, DR <= nd nr,
+ * RR <= nr(nr-1)/2), else CUTE_E_INVALID_ARG. */
 cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, const uint64_t* dr,
                              const uint64_t* rr, int64_t nd, int64_t nr,
                              const cute_binning* bins, double box_size, double* xi);
@@ -419,6 +421,30 @@ cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, const uint64_
  * with l outer. */
 cute_status cute_xi_multipoles(const double* xi_rmu, const cute_binning* bins, int32_t n_ell,
                                const int32_t* ells, double* out);
+
+/* Host-only diagnostic: the FP32 decision constants of the midpoint line of
+ * sight (SIGMAPI, or RMU with CUTE_LOS_MIDPOINT; mu, pi = r mu and
+ * sigma = sqrt(r^2 - pi^2) of Sec. 2.1 measured against l = p + q), built
+ * exactly as a count builds them, for a given FP32 error model. No device
+ * work. It exists so that the rounding analysis behind the exact FP32 path can
+ * be checked against exact arithmetic without a GPU.
+ * err[4]: bounds per component on |FP32 s - s| (s = p - q), on |FP64 s - s|,
+ * on |FP32 l - l| and on |FP64 l - l|.
+ * band1: 2 * n1 floats, band2: 2 * n2 floats; per bin the threshold w of its
+ * lower edge, then that of its upper edge: a pair is certified in the bin
+ * along that dimension when F + w_lo ll >= t and F + w_hi ll <= -t, with
+ * F = |s x l|^2 (sigma) or (s.l)^2 (pi), ll = |l|^2 and t = K1 |l| + K0
+ * (SIGMAPI; for RMU the mu thresholds are the plain -mu_j^2 and the band is
+ * delta below).
+ * consts: 17 floats: skip32 (pairs with FP32 |s|^2 >= skip32 are out of
+ * range), llg (pairs with ll < llg are never decided in FP32), K1, K0,
+ * w of sigma_max, of pi_max, of sigma_0, of pi_0, the low-side flag, then the
+ * mu band coefficients A0 A1 A2 B0 B1 B2 C2 C0 of
+ * delta = ll (A2 v + A1 r + A0) + |l| (B2 v + B1 r + B0) + C2 v + C0.
+ * Errors: CUTE_E_INVALID_ARG (bad binning, NULL, negative or non-finite
+ * error bounds), CUTE_E_UNSUPPORTED (other binnings). */
+cute_status cute_fp32_decision_tables(const cute_binning* bins, const double* err,
+                                      float* band1, float* band2, float* consts);
 
 const char* cute_status_string(cute_status s);
 

@@ -32,7 +32,8 @@ EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_cou
             "cute_batch_stats", "cute_batch_free", "cute_count_pairs_batched", "cute_count_jackknife",
             "cute_count_jackknife_cross",
             "cute_build_pixel_map", "cute_pixel_map_read", "cute_count_radial",
-            "cute_xi_estimate", "cute_xi_multipoles", "cute_status_string", "cute_last_error"]
+            "cute_xi_estimate", "cute_xi_multipoles", "cute_fp32_decision_tables",
+            "cute_status_string", "cute_last_error"]
 
 
 class CuteError(RuntimeError):
@@ -149,6 +150,8 @@ def load():
     lib.cute_xi_multipoles.restype = ctypes.c_int
     lib.cute_xi_multipoles.argtypes = [dp, ctypes.POINTER(CBinning), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32), dp]
+    lib.cute_fp32_decision_tables.restype = ctypes.c_int
+    lib.cute_fp32_decision_tables.argtypes = [ctypes.POINTER(CBinning), dp, vp, vp, vp]
     lib.cute_status_string.restype = ctypes.c_char_p
     lib.cute_status_string.argtypes = [ctypes.c_int]
     lib.cute_last_error.restype = ctypes.c_char_p
@@ -665,3 +668,24 @@ def xi_multipoles(xi_rmu, binning: Binning, ells=(0, 2, 4)):
                                   e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+DECISION_CONSTS = ("skip32", "llg", "K1", "K0", "w_sigma_top", "w_pi_top", "w_sigma_bottom",
+                   "w_pi_bottom", "low", "A0", "A1", "A2", "B0", "B1", "B2", "C2", "C0")
+
+
+def fp32_decision_tables(binning: Binning, ec: float, ec64: float, el: float, el64: float):
+    """cute_fp32_decision_tables (host only): the FP32 thresholds of the
+    midpoint predicates for a given error model, as (band1 [n1, 2],
+    band2 [n2, 2], dict of constants)."""
+    lib = load()
+    cb = binning.c()
+    err = np.array([ec, ec64, el, el64], dtype=np.float64)
+    n1, n2 = binning.shape[0], binning.shape[1] if len(binning.shape) > 1 else 0
+    b1 = np.zeros((n1, 2), dtype=np.float32)
+    b2 = np.zeros((max(n2, 1), 2), dtype=np.float32)
+    c = np.zeros(len(DECISION_CONSTS), dtype=np.float32)
+    _check(lib.cute_fp32_decision_tables(ctypes.byref(cb),
+                                         err.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         b1.ctypes.data, b2.ctypes.data, c.ctypes.data))
+    return b1, b2[:n2], dict(zip(DECISION_CONSTS, c.tolist()))

@@ -53,6 +53,8 @@ template <typename T>
 cute_status owned_alloc(cute_batch* b, T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
+    if (inject_alloc_failure())
+        return fail(CUTE_E_OUT_OF_MEMORY, "device allocation refused (CUTE_TEST_FAIL_ALLOC)");
     hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
     if (e != hipSuccess) return hip_status(e, "hipMalloc");
     b->owned.push_back(*p);

@@ -183,7 +183,11 @@ cute_status launch_b(const BatchArgs& ba, int grid, size_t lds, hipStream_t s) {
 // Dispatch on (mode, prec, est) to F<MODE, PREC, EST>(args...).
 #define CUTE_DISPATCH(FN, mode, prec, est, ...)                                              \
     do {                                                                                      \
-        const int m_ = (mode), p_ = (prec), e_ = (est);                                       \
+        const int m_ = (mode), p_ = (prec), e_ = (est) & E_LOG;                               \
+        if (m_ == M_RMU_Z && p_ == P_FP32E && est_muf(est)) {                                 \
+            if (e_) return FN<1, 1, E_LOG | E_MUF>(__VA_ARGS__);                                \
+            return FN<1, 1, E_MUF>(__VA_ARGS__);                                               \
+        }                                                                                     \
         switch (m_ * 6 + p_ * 2 + e_) {                                                       \
             case 0: return FN<0, 0, 0>(__VA_ARGS__);                                          \
             case 1: return FN<0, 0, 1>(__VA_ARGS__);                                          \

@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <atomic>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -31,6 +33,12 @@ cute_status hip_status(hipError_t e, const char* what) {
     return fail(CUTE_E_DEVICE, m);
 }
 
+// The library's pool per device: freed blocks up to kPoolKeep bytes stay
+// reserved for the next call; beyond that they go back to the device at the
+// next synchronisation (large grids do not stay reserved after they are freed).
+constexpr uint64_t kPoolKeep = 256ull << 20;
+static hipMemPool_t g_pool[64] = {};
+
 cute_status ensure_device_ready(int* device) {
     static std::mutex mu;
     static bool ready[64] = {false};
@@ -39,12 +47,44 @@ cute_status ensure_device_ready(int* device) {
     *device = dev;
     std::lock_guard<std::mutex> lk(mu);
     if (dev >= 0 && dev < 64 && !ready[dev]) {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t thr = UINT64_MAX;
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+            uint64_t thr = kPoolKeep;
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            g_pool[dev] = pool;
         }
         ready[dev] = true;
+    }
+    return CUTE_OK;
+}
+
+bool inject_alloc_failure() {
+    static std::atomic<uint64_t> calls{0};
+    const char* v = std::getenv("CUTE_TEST_FAIL_ALLOC");
+    if (v == nullptr) return false;
+    const long n = std::strtol(v, nullptr, 10);
+    if (n <= 0) return false;
+    return (calls.fetch_add(1) + 1) % (uint64_t)n == 0;
+}
+
+cute_status dev_malloc_async(void** p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    if (inject_alloc_failure())
+        return fail(CUTE_E_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) +
+                                              " bytes refused (CUTE_TEST_FAIL_ALLOC)");
+    int dev = 0;
+    CUTE_HIP(hipGetDevice(&dev));
+    hipMemPool_t pool = (dev >= 0 && dev < 64) ? g_pool[dev] : nullptr;
+    hipError_t e = pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_status(e, "device allocation");
     }
     return CUTE_OK;
 }
@@ -562,6 +602,41 @@ extern "C" cute_status cute_tune_grid(const double* x, const double* y, const do
 // __int128 -> double through the compiler's correctly rounded conversion
 static double i128_to_double(__int128 v) { return static_cast<double>(v); }
 
+extern "C" cute_status cute_fp32_decision_tables(const cute_binning* bins, const double* err,
+                                                 float* band1, float* band2, float* consts) {
+    cute_status s;
+    if ((s = validate_binning(bins)) != CUTE_OK) return s;
+    const bool mid = bins->kind == CUTE_BIN_SIGMAPI ||
+                     (bins->kind == CUTE_BIN_RMU && bins->los == CUTE_LOS_MIDPOINT);
+    if (!mid) return fail(CUTE_E_UNSUPPORTED, "decision tables are reported for the midpoint line of sight only");
+    if (!err || !band1 || !band2 || !consts) return fail(CUTE_E_INVALID_ARG, "NULL argument");
+    for (int k = 0; k < 4; k++)
+        if (!std::isfinite(err[k]) || err[k] < 0.0)
+            return fail(CUTE_E_INVALID_ARG, "error bounds must be finite and >= 0");
+    Plan pl;
+    plan_binning(bins, pl);
+    ErrModel em;
+    em.ec = err[0];
+    em.ec64 = err[1];
+    em.el = err[2];
+    em.el64 = err[3];
+    plan_bands(bins, em, pl);
+    for (int k = 0; k < bins->n1; k++) {
+        band1[2 * k] = pl.band1[k].x;
+        band1[2 * k + 1] = pl.band1[k].y;
+    }
+    for (int k = 0; k < bins->n2; k++) {
+        band2[2 * k] = pl.band2[k].x;
+        band2[2 * k + 1] = pl.band2[k].y;
+    }
+    const CountArgs& a = pl.a;
+    const float c[kDecisionConsts] = {a.skip32, a.llg, a.spK1, a.spK0, a.sp_wstop, a.sp_wptop,
+                                      a.sp_wsbot, a.sp_wpbot, (float)a.sp_low, a.dA0, a.dA1, a.dA2,
+                                      a.dB0, a.dB1, a.dB2, a.dC2, a.dC0};
+    for (int k = 0; k < kDecisionConsts; k++) consts[k] = c[k];
+    return CUTE_OK;
+}
+
 extern "C" cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, const uint64_t* dr,
                                         const uint64_t* rr, int64_t nd, int64_t nr,
                                         const cute_binning* bins, double box_size, double* xi) {
@@ -589,8 +664,16 @@ extern "C" cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, co
     if (!rr) return fail(CUTE_E_INVALID_ARG, "rr is NULL");
     if (e == CUTE_EST_LS && !dr) return fail(CUTE_E_INVALID_ARG, "dr is NULL");
     if (nd < 2 || nr < 2) return fail(CUTE_E_INVALID_ARG, "nd and nr must be >= 2");
-    if (nd > ((int64_t)1 << 40) || nr > ((int64_t)1 << 40))
-        return fail(CUTE_E_INVALID_ARG, "catalog sizes too large for exact arithmetic");
+    // With nd, nr < 2^31 (the size limit of a grid) and every count at most
+    // the number of pairs it can hold (DD <= nd(nd-1)/2, DR <= nd nr,
+    // RR <= nr(nr-1)/2), each product below is under 2^124 and the
+    // numerator N_r(N_r-1)DD - (N_r-1)(N_d-1)DR + N_d(N_d-1)RR lies in
+    // (-2^124, 2^124): no 128-bit overflow.
+    if (nd >= ((int64_t)1 << 31) || nr >= ((int64_t)1 << 31))
+        return fail(CUTE_E_INVALID_ARG, "catalog sizes must be below 2^31");
+    const uint64_t max_dd = (uint64_t)nd * (uint64_t)(nd - 1) / 2u;
+    const uint64_t max_rr = (uint64_t)nr * (uint64_t)(nr - 1) / 2u;
+    const uint64_t max_dr = (uint64_t)nd * (uint64_t)nr;
     const __int128 cdd = (__int128)nr * (nr - 1);   // multiplies DD
     const __int128 cdr = (__int128)(nr - 1) * (nd - 1);
     const __int128 crr = (__int128)nd * (nd - 1);   // multiplies RR (and the denominator)
@@ -599,9 +682,10 @@ extern "C" cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, co
             xi[k] = NAN;
             continue;
         }
-        if (dd[k] > ((uint64_t)1 << 62) || rr[k] > ((uint64_t)1 << 62) ||
-            (dr && dr[k] > ((uint64_t)1 << 62)))
-            return fail(CUTE_E_INVALID_ARG, "counts too large for exact arithmetic");
+        if (dd[k] > max_dd || rr[k] > max_rr || (dr && dr[k] > max_dr))
+            return fail(CUTE_E_INVALID_ARG,
+                        "a count exceeds the number of pairs of its catalogs (DD <= nd(nd-1)/2, "
+                        "DR <= nd nr, RR <= nr(nr-1)/2)");
         __int128 num, den = crr * (__int128)rr[k];
         if (e == CUTE_EST_NATURAL)
             num = cdd * (__int128)dd[k] - crr * (__int128)rr[k];

@@ -136,9 +136,9 @@ __device__ __forceinline__ int guess1(const CountArgs& P, float v) {
     if (MODE == M_THETA) {
         float c = __builtin_amdgcn_sqrtf(v);
         float th = fmaf(c * v, 1.0f / 24.0f, c);  // 2 asin(c/2) to third order
-        t = (EST == E_LOG) ? __builtin_amdgcn_logf(th) : th;
+        t = est_log(EST) ? __builtin_amdgcn_logf(th) : th;
     } else {
-        t = (EST == E_LOG) ? __builtin_amdgcn_logf(v) : __builtin_amdgcn_sqrtf(v);
+        t = est_log(EST) ? __builtin_amdgcn_logf(v) : __builtin_amdgcn_sqrtf(v);
     }
     return (int)__builtin_amdgcn_fmed3f(fmaf(t, P.e1a, P.e1b), 0.0f, P.n1m1);
 }
@@ -227,10 +227,11 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p;
 }
 
+template <int EST>
 __device__ __forceinline__ Tab32 make_tab32(const CountArgs& P, const float2* B1, const float2* B2) {
     Tab32 t;
     asm volatile("v_mov_b32 %0, %1" : "=v"(t.vbias) : "s"(kBias));
-    asm volatile("v_mov_b32 %0, %1" : "=v"(t.d0) : "s"(P.dA0p));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t.d0) : "s"(est_muf(EST) ? P.muB0 : P.dA0p));
     t.tb1 = lds_addr(B1) - (kBias << 3);
     t.tb2 = lds_addr(B2) - (kBias << 3);
     return t;
@@ -270,8 +271,8 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         if (MODE == M_THETA) {
             float ch = __builtin_amdgcn_sqrtf(v);
             float th = fmaf(ch * v, 1.0f / 24.0f, ch);  // 2 asin(c/2) to third order
-            ts = ((EST == E_LOG) ? __builtin_amdgcn_logf(th) : th) + P.s1;
-        } else if (EST == E_LOG) {
+            ts = (est_log(EST) ? __builtin_amdgcn_logf(th) : th) + P.s1;
+        } else if (est_log(EST)) {
             ts = __builtin_amdgcn_logf(v) + P.s1;
         } else {
             ts = fmaf(v, __builtin_amdgcn_rsqf(v), P.s1);
@@ -285,19 +286,32 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
     }
     if (MODE == M_RMU_Z) {
         float rinv = __builtin_amdgcn_rsqf(v);
-        float ts = (EST == E_LOG) ? __builtin_amdgcn_logf(v) + P.s1 : fmaf(v, rinv, P.s1);
+        float ts = est_log(EST) ? __builtin_amdgcn_logf(v) + P.s1 : fmaf(v, rinv, P.s1);
         c.kb = est_bits(ts, P.e1a, T, P.top1);
-        c.kmb = est_bits(fmaf(fabsf(dz), rinv, P.s2), P.e2a, T, P.top2);
+        float ts2 = fmaf(fabsf(dz), rinv, P.s2);
+        c.kmb = est_bits(ts2, P.e2a, T, P.top2);
         float dz2 = dz * dz;
         float2 b = band_at(T.tb1, c.kb);
-        float2 m = band_at(T.tb2, c.kmb);
-        // band of the mu predicates, linear in r: dA1 r + dA0. With linear r
-        // bins ts = r + s1 and the host folds -dA1 s1 into the constant.
-        float delta = (EST == E_LOG) ? fmaf(P.dA1, v * rinv, T.d0) : fmaf(P.dA1, ts, T.d0);
-        float flo = fmaf(m.x, v, dz2);
-        float fhi = fmaf(m.y, v, dz2);
         bool rin = (v >= b.x) & (v < b.y);
-        bool min_ = (flo >= delta) & (fhi <= -delta);
+        bool min_;
+        if (est_muf(EST) && !WANT_TENT) {
+            // in mu space: tq = mu a + b is the pair's position in bin units
+            // (ts2 a = tq - 1/2); the pair is inside bin floor(tq) when the
+            // fraction of tq is at least beta(r) = muB0' + |muB1| / r from
+            // both edges (T.d0 = 1/2 - muB0', the band kept as a half-width)
+            float tq = fmaf(ts2, P.e2a, 0.5f);
+            float fr = __builtin_amdgcn_fractf(tq);
+            float half = fmaf(P.muB1, rinv, T.d0);
+            min_ = fabsf(fr - 0.5f) <= half;
+        } else {
+            float2 m = band_at(T.tb2, c.kmb);
+            // band of the mu predicates, linear in r: dA1 r + dA0. With linear
+            // r bins ts = r + s1 and the host folds -dA1 s1 into the constant.
+            float delta = est_log(EST) ? fmaf(P.dA1, v * rinv, T.d0) : fmaf(P.dA1, ts, T.d0);
+            float flo = fmaf(m.x, v, dz2);
+            float fhi = fmaf(m.y, v, dz2);
+            min_ = (flo >= delta) & (fhi <= -delta);
+        }
         c.in = rin & min_;
         // only r decides a clean "out"; a pair outside a partial mu range is
         // re-tested instead (never the case for mu in [0, 1])
@@ -315,7 +329,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
         float rinv = __builtin_amdgcn_rsqf(v);
         float r = v * rinv;
-        float ts = (EST == E_LOG) ? __builtin_amdgcn_logf(v) + P.s1 : r + P.s1;
+        float ts = est_log(EST) ? __builtin_amdgcn_logf(v) + P.s1 : r + P.s1;
         c.kb = est_bits(ts, P.e1a, T, P.top1);
         float w = v * ll;
         float sl2 = sl * sl;
@@ -332,7 +346,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         float fhi = fmaf(m.y, w, sl2);
         bool rin = (v >= b.x) & (v < b.y);
         bool min_ = (flo >= delta) & (fhi <= -delta);
-        c.in = rin & min_;
+        c.in = rin & min_ & (ll >= P.llg);
         c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);
         if (WANT_TENT) {
             bool rr = v >= P.bot32 & v < P.top32;
@@ -347,34 +361,38 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
     float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
     float sl2 = sl * sl;
     float c2 = fmaf(v, ll, -sl2);
-    // sigma = sqrt(c2) / |l| and pi = |s.l| / |l| share one 1/|l|: three
-    // quarter-rate operations per pair (rsq, two sqrt) instead of five
+    // sigma = sqrt(c2) / |l| and pi = |s.l| / |l| share one 1/|l|
     float rl = __builtin_amdgcn_rsqf(ll);
-    float lnorm = ll * rl;
     float sg = __builtin_amdgcn_sqrtf(fmaxf(c2, 0.0f)) * rl;
     float pp = fabsf(sl) * rl;
     c.kb = est_bits(sg + P.s1, P.e1a, T, P.top1);
     c.kmb = est_bits(pp + P.s2, P.e2a, T, P.top2);
-    float t = __builtin_amdgcn_sqrtf(v);
-    float ds = fmaf(ll, fmaf(P.sA2, v, fmaf(P.sA1, t, P.sA0)),
-                    fmaf(lnorm, fmaf(P.sB2, v, fmaf(P.sB1, t, P.sB0)), fmaf(P.sC2, v, P.sC0)));
-    float dp = fmaf(ll, fmaf(P.dA2, v, fmaf(P.dA1, t, P.dA0)),
-                    fmaf(lnorm, fmaf(P.dB2, v, fmaf(P.dB1, t, P.dB0)), fmaf(P.dC2, v, P.dC0)));
-    float2 bs = band_at(T.tb1, c.kb);
-    float2 bp = band_at(T.tb2, c.kmb);
-    float fslo = fmaf(bs.x, ll, c2), fshi = fmaf(bs.y, ll, c2);
-    float fplo = fmaf(bp.x, ll, sl2), fphi = fmaf(bp.y, ll, sl2);
-    c.in = (fslo >= ds) & (fshi <= -ds) & (fplo >= dp) & (fphi <= -dp);
-    // out of range: sigma >= sigma_max, pi >= pi_max, or below the first edges
-    float fstop = fmaf(P.out_hi, ll, c2);       // out_hi holds -S2f[n1]
-    float fptop = fmaf(P.nhi2_last, ll, sl2);   // -P2f[n2]
-    float fsbot = fmaf(P.out_lo, ll, c2);       // out_lo holds -S2f[0] (or +BIG)
-    float fpbot = fmaf(P.nlo2_first, ll, sl2);  // -P2f[0] (or +BIG)
-    c.out = (fstop >= ds) | (fptop >= dp) | (fsbot <= -ds) | (fpbot <= -dp);
     if (WANT_TENT) {
+        // out of range: sigma >= sigma_max, pi >= pi_max, or below the first edges
+        float fstop = fmaf(P.out_hi, ll, c2);       // out_hi holds -S2f[n1]
+        float fptop = fmaf(P.nhi2_last, ll, sl2);   // -P2f[n2]
+        float fsbot = fmaf(P.out_lo, ll, c2);       // out_lo holds -S2f[0] (or +BIG)
+        float fpbot = fmaf(P.nlo2_first, ll, sl2);  // -P2f[0] (or +BIG)
         bool ok = (fsbot >= 0.0f) & (fstop < 0.0f) & (fpbot >= 0.0f) & (fptop < 0.0f);
         *tent = ok ? c32_bin(P, c) : kNoBin;
+        c.in = c.out = false;
+        return c;
     }
+    // the per-edge parts of the bands are in the tables (F + w ll); the part
+    // from the direction error of l is t, in units of F
+    float t = fmaf(P.spK1, ll * rl, P.spK0);
+    float2 bs = band_at(T.tb1, c.kb);
+    float2 bp = band_at(T.tb2, c.kmb);
+    // |s| below the skip threshold bounds every error term; ll >= llg bounds
+    // the direction error of l
+    bool vin = v < P.skip32;
+    bool lg = ll >= P.llg;
+    bool ins = (fmaf(bs.x, ll, c2) >= t) & (fmaf(bs.y, ll, c2) <= -t);
+    bool inp = (fmaf(bp.x, ll, sl2) >= t) & (fmaf(bp.y, ll, sl2) <= -t);
+    c.in = vin & lg & ins & inp;
+    bool top = (fmaf(P.sp_wstop, ll, c2) >= t) | (fmaf(P.sp_wptop, ll, sl2) >= t);
+    if (LO) top = top | (fmaf(P.sp_wsbot, ll, c2) <= -t) | (fmaf(P.sp_wpbot, ll, sl2) <= -t);
+    c.out = !vin | (lg & top);
     return c;
 }
 
@@ -462,7 +480,7 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
             const float qx = b.x - (P.offx - shift32(code, 0, Lf));
             const float qy = b.y - (P.offy - shift32(code, 1, Lf));
             const float qz = b.z - (P.offz - shift32(code, 2, Lf));
-            const Tab32 tab = make_tab32(P, B1, B2);
+            const Tab32 tab = make_tab32<EST>(P, B1, B2);
             (void)classify32<MODE, EST, true>(P, tab, a.x - qx, a.y - qy, a.z - qz,
                                               a.x + (qx + P.lcx), a.y + (qy + P.lcy),
                                               a.z + (qz + P.lcz), &t);
@@ -803,7 +821,7 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
 #undef CUTE_RUN64
     } else {
         // wave-uniform constants in VGPRs, and this lane's histogram copy
-        const Tab32 tab = make_tab32(P, B1, B2);
+        const Tab32 tab = make_tab32<EST>(P, B1, B2);
         const uint32_t lb = lds_addr(W.hist) + ((uint32_t)lane & (uint32_t)(P.copies - 1)) * 8u;
         // the neighbour in the home grid's FP32 frame: q - (cA - cB) for two
         // open grids, or its periodic image q + k L (only one of the two is
@@ -835,7 +853,7 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
         // the home offsets with any (queued once the home loop is done)
         uint64_t ambh = 0, hsum = 0;
         // bins starting at zero separation have no low-side clean "out"
-        const bool low = !(P.out_lo < 0.0f) || MODE == M_SIGMAPI;
+        const bool low = MODE == M_SIGMAPI ? P.sp_low != 0 : !(P.out_lo < 0.0f);
         if (C.masked) {
             if (low) CUTE_RUN32(true, true) else CUTE_RUN32(true, false)
         } else {
@@ -1133,6 +1151,12 @@ __device__ void do_tile(const CountArgs& P, WaveState& W, SpanBuf& S, const floa
                         const float2* B2, const double* T1, const double* T2, int lane,
                         const Tile& tl) {
     W.tiles++;
+    if (PM && P.mbA != nullptr) {
+        // a tile whose home points are all masked out has no pair to count
+        const uint32_t i = tl.start + (uint32_t)lane;
+        const bool live = i < tl.end && ((P.mbA[i >> 5] >> (i & 31u)) & 1u) == 0u;
+        if (__builtin_amdgcn_ballot_w64(live) == 0ull) return;
+    }
     Chunk C;
     C.filled = 0;
     C.masked = false;

@@ -146,13 +146,18 @@ cute_status launch_est(const CountArgs& a, int est, int wg_waves, size_t lds, hi
     if (a.wA != nullptr) {
         // weighted pairs: the angular kernels only (pixel maps)
         if constexpr (MODE == M_THETA) {
-            if (est == E_LOG) return launch_one<MODE, PREC, E_LOG, true>(a, wg_waves, lds, s, g);
+            if (est_log(est)) return launch_one<MODE, PREC, E_LOG, true>(a, wg_waves, lds, s, g);
             return launch_one<MODE, PREC, E_LIN, true>(a, wg_waves, lds, s, g);
         } else {
             return fail(CUTE_E_UNSUPPORTED, "weighted pairs need a THETA binning");
         }
     }
-    if (est == E_LOG) return launch_one<MODE, PREC, E_LOG, false>(a, wg_waves, lds, s, g);
+    if constexpr (MODE == M_RMU_Z && PREC == P_FP32E) {
+        // the mu decision in mu space (FP32_EDGE only)
+        if (est == (E_LOG | E_MUF)) return launch_one<MODE, PREC, E_LOG | E_MUF, false>(a, wg_waves, lds, s, g);
+        if (est == E_MUF) return launch_one<MODE, PREC, E_MUF, false>(a, wg_waves, lds, s, g);
+    }
+    if (est_log(est)) return launch_one<MODE, PREC, E_LOG, false>(a, wg_waves, lds, s, g);
     return launch_one<MODE, PREC, E_LIN, false>(a, wg_waves, lds, s, g);
 }
 

@@ -26,7 +26,13 @@ constexpr int kWgWaves = 4;       // waves per count workgroup
 // Kinds of pair classification the kernels are specialised for.
 enum Mode : int { M_MONO = 0, M_RMU_Z = 1, M_RMU_MID = 2, M_SIGMAPI = 3, M_THETA = 4, M_RADIAL = 5 };
 // How a bin index is estimated from the squared separation.
-enum Est : int { E_LIN = 0, E_LOG = 1 };
+// Estimate flags of a count kernel: bit 0, dimension 1 (r or theta) is
+// estimated from log(d2) (log-spaced edges) rather than linearly; bit 1, the
+// mu decision of the z line of sight is taken in mu space (linear mu edges
+// covering [0, 1]), FP32_EDGE only.
+enum Est : int { E_LIN = 0, E_LOG = 1, E_MUF = 2 };
+constexpr bool est_log(int e) { return (e & E_LOG) != 0; }
+constexpr bool est_muf(int e) { return (e & E_MUF) != 0; }
 // Precision path.
 enum Prec : int { P_FP64 = 0, P_FP32E = 1, P_FP32O = 2 };
 
@@ -86,12 +92,21 @@ struct CountArgs {
     float bot32, top32;             // FP32-rounded T1[0], T1[n1] (tentative decisions)
     float d2lo32, d2hi32;           // FP32-rounded T2[0], T2[n2]
     float nlo2_first, nhi2_last;    // -T2f[0] (or +BIG), -T2f[n2] (or -BIG) for dim-2 range
-    // rounding band of the ratio predicates (mu, pi, sigma), per pair:
-    //   delta = ll (A2 v + A1 r + A0) + |l| (B2 v + B1 r + B0) + C2 v
-    // with ll = |l|^2 = 1 and |l| = 0 for the z line of sight
-    //   + C2 v + C0
-    float dA0, dA1, dA2, dB0, dB1, dB2, dC2, dC0;  // mu (RMU) or pi (SIGMAPI)
-    float sA0, sA1, sA2, sB0, sB1, sB2, sC2, sC0;  // sigma (SIGMAPI)
+    // rounding band of the mu predicates, per pair. Midpoint line of sight:
+    //   delta = ll (A2 v + A1 r + A0) + |l| (B2 v + B1 r + B0) + C2 v + C0;
+    // z line of sight: delta = A1 r + A0 (dA0p below)
+    float dA0, dA1, dA2, dB0, dB1, dB2, dC2, dC0;
+    // midpoint line of sight: a pair is decided in FP32 only when
+    // ll = |l|^2 >= llg (the direction of l is then known to a bounded angle)
+    float llg;
+    // sigma-pi: the per-edge parts of the rounding bands sit in the band
+    // tables; the per-pair part is t = spK1 |l| + spK0, and a decision
+    // F + w ll against +-t (F = |s x l|^2 or (s.l)^2). Out of range: sigma or
+    // pi at or past its top edge (wstop, wptop), below its first edge (wsbot,
+    // wpbot, tested only when sp_low)
+    float spK1, spK0;
+    float sp_wstop, sp_wptop, sp_wsbot, sp_wpbot;
+    int sp_low;
     // tables (global; staged into LDS)
     const float2* band1;            // n1 entries: (lo_k, hi_{k+1}) FP32 band thresholds of dim 1
     const float2* band2;            // n2 entries: (-T2f[k] or +BIG, -T2f[k+1] or -BIG)
@@ -109,6 +124,10 @@ struct CountArgs {
     // constant term of the mu band of the z line of sight as the kernel uses
     // it (dA0 for log r bins, dA0 - dA1 s1 plus its rounding for linear ones)
     float dA0p;
+    // mu in mu space (E_MUF): a pair is inside its mu bin when the fraction
+    // f of its position in bin units satisfies |f - 1/2| <= muB1 / r + muB0
+    // (muB1 < 0: the band grows as the separation shrinks)
+    float muB1, muB0;
     // precomputed neighbour rows (see ItemGeom::stencil), or nullptr
     const int4* stencil;
     int nst;
@@ -210,6 +229,9 @@ struct ItemGeom {
 };
 
 // A count launch: thresholds, band tables and the binning's kernel constants.
+// number of floats cute_fp32_decision_tables writes to consts
+constexpr int kDecisionConsts = 17;
+
 struct Plan {
     int mode = 0, est = 0;
     double rmax = 0.0;               // largest countable separation

@@ -20,6 +20,9 @@ constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 constexpr float kBig = 1e30f;
 constexpr double kPiH = 3.14159265358979323846;
 constexpr uint32_t kBiasBits = 0x4B000000u;       // bits of the float 2^23
+// largest relative error assumed of the hardware 1/sqrt (v_rsq_f32); it is
+// documented at 1 ulp (2^-23), so this keeps a factor 4
+constexpr double kRsqRel = 0x1p-21;
 
 float up32(double x) {
     float f = (float)x;
@@ -362,6 +365,143 @@ ErrModel max_err(const ErrModel& x, const ErrModel& y) {
     return m;
 }
 
+// Rounding bands of the midpoint line of sight (sigma, pi and mu against the
+// pair midpoint, Sec. 2.1 with l = p + q). Every constant below is a term of
+// the bound derived in the design notes; the FP32 operation order it assumes
+// is the one of classify32. Notation: s = p - q and l = p + q of the FP64
+// inputs (exact reals); the FP32 vectors carry |s32 - s| <= es and
+// |l32 - l| <= fe (norms); x is sigma or pi, T an edge's squared value;
+// Rv bounds |s| for every pair the FP32 path decides (v32 < skip32); the
+// direction error of l is phi = fe / |l| <= 1/15 once ll >= llg.
+//   |x32^2 - x^2| <= 2 x Dx + Dx^2,  Dx = es + 2 r phi   (x32 of the FP32 inputs)
+// (x = |s.n| or |s x n| with n = l / |l|, and |n32 - n| <= 2 phi). Split into
+// a per-edge part that multiplies ll and goes into the band tables,
+//   b(T) = M [2 x' es + es^2 + E64 + cu u Rv^2 + 6 u T],  x' = sqrt(T + E64),
+// with cu the rounding of the FP32 products (14 for sigma: |s|^2 |l|^2 -
+// (s.l)^2 with both terms rounded; 8 for pi: (s.l)^2) and 6 u T the rounding
+// of ll, of the threshold product and of the final fma, and a per-pair part
+// in the units of F (t = K1 |l| + K0) for the terms in phi:
+//   ll (4 (x + es) r phi + 4 r^2 phi^2) <= K1 |l32| + K0.
+// E64 bounds the canonical FP64 decision's own deviation from exact reals.
+static void midpoint_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
+    CountArgs& a = pl.a;
+    const int n1 = b->n1, n2 = b->n2;
+    const double s3 = std::sqrt(3.0), u = kU32;
+    const double es = s3 * em.ec;            // |s32 - s|
+    const double fe = s3 * em.el;            // |l32 - l|
+    const double kg = 16.0;                  // guard: |l32| >= kg fe
+    const double ig = 1.0 / (1.0 - 1.0 / kg);
+    const double lrel = 1.0 + 2.0 * kRsqRel; // |l32| <= fl(ll rsq(ll)) (1 + 2^-20)
+    const double M = 1.25;                   // safety factor on the derived bound
+    a.llg = up32(kg * kg * fe * fe * (1.0 + 4 * u));
+    if (pl.mode == M_SIGMAPI) {
+        // |s| of any pair with v32 < skip32 (skip32 covers the FP32 and FP64
+        // errors of d2 up to there)
+        const double Rv = std::sqrt((double)a.skip32 * (1.0 + 3.02 * u)) + es;
+        const double Tmax = std::max(pl.T1[n1], pl.T2[n2]);
+        const double E64 = 64.0 * kU64 * (Rv * Rv + Tmax);
+        const double xmax = std::sqrt(Tmax + E64) * (1.0 + 1e-9);
+        a.spK1 = up32((1.0 + 4 * u) * 4.0 * (xmax + es) * Rv * fe * lrel * ig);
+        a.spK0 = up32((1.0 + 4 * u) * 4.0 * Rv * Rv * fe * fe * ig * ig + 1e-30);
+        auto band = [&](double T, double cu) {
+            const double x = std::sqrt(T + E64) * (1.0 + 1e-9);
+            return M * (2 * x * es + es * es + E64 + cu * u * Rv * Rv + 6 * u * T + 1e-30) /
+                   (1.0 - 6 * u);
+        };
+        std::vector<double> bs(n1 + 1), bp(n2 + 1);
+        for (int k = 0; k <= n1; k++) bs[k] = band(pl.T1[k], 14.0);
+        for (int k = 0; k <= n2; k++) bp[k] = band(pl.T2[k], 8.0);
+        // bin k: F + wlo ll >= t certifies x^2 >= T_k (a first edge at zero
+        // always holds: +BIG); F + whi ll <= -t certifies x^2 < T_{k+1}
+        // (an upper edge inside its own band, T <= b, is never certified: +BIG)
+        auto lo_w = [](double T, double bb) { return T == 0.0 ? kBig : dn32(-(T + bb)); };
+        auto hi_w = [](double T, double bb) { return T - bb <= 0.0 ? kBig : up32(-(T - bb)); };
+        pl.band1.resize(n1);
+        for (int k = 0; k < n1; k++)
+            pl.band1[k] = make_float2(lo_w(pl.T1[k], bs[k]), hi_w(pl.T1[k + 1], bs[k + 1]));
+        pl.band2.resize(n2);
+        for (int k = 0; k < n2; k++)
+            pl.band2[k] = make_float2(lo_w(pl.T2[k], bp[k]), hi_w(pl.T2[k + 1], bp[k + 1]));
+        a.sp_wstop = dn32(-(pl.T1[n1] + bs[n1]));
+        a.sp_wptop = dn32(-(pl.T2[n2] + bp[n2]));
+        a.sp_wsbot = hi_w(pl.T1[0], bs[0]);
+        a.sp_wpbot = hi_w(pl.T2[0], bp[0]);
+        a.sp_low = (pl.T1[0] > 0.0 || pl.T2[0] > 0.0) ? 1 : 0;
+        return;
+    }
+    // mu against the midpoint: G = pi^2 - T r^2 (T = mu_j^2 <= 1). With
+    // |pi32 - pi| <= es + 2 r phi and |r32^2 - r^2| <= 2 r es + es^2:
+    //   |G32 - G| <= 2 r es (mu + T) + es^2 (1 + T) + 4 mu r^2 phi
+    //               + 4 r es phi + 4 r^2 phi^2 <= 4 r es + 2 es^2 + 4 r^2 phi + ...
+    // and the FP32 evaluation (s.l)^2 - T fl(v ll) errs by at most
+    // (6.02 + 1 + 8.04) u r^2 |l|^2. In the kernel's form
+    //   delta = ll (A2 v + A1 r + A0) + |l| (B2 v + B1 r + B0) + C2 v + C0,
+    // with r the FP32 estimate fl(v rsq(v)) and v = fl(|s32|^2):
+    // |s| <= r (1 + 2^-20) + es, |s|^2 <= v (1 + 3.02 u) + 2 r es + es^2.
+    const double Rv = pl.rmax * (1.0 + 1e-6) + es;
+    const double E64 = 64.0 * kU64 * (Rv * Rv + 1.0);
+    const double rr = 1.0 + 2.0 * kRsqRel, vv = (1.0 + 3.02 * u) / (1.0 - 3.02 * u);
+    const double A1 = 4 * es * rr;
+    const double A2 = 15.1 * u * vv;
+    const double A0 = 4 * es * es + 2 * es * es + E64 * (1.0 + 1e-9);
+    // l terms: ll phi <= fe |l32| lrel ig, ll phi^2 <= fe^2 ig^2
+    const double fl1 = fe * lrel * ig, fl2 = fe * fe * ig * ig;
+    const double B2 = 4 * fl1 * vv;                       // 4 r^2 phi ll
+    const double B1 = (8 + 4) * fl1 * es * rr;            // 4 (2 r es) + 4 r es (phi ll)
+    const double B0 = (4 + 4) * fl1 * es * es;
+    const double C2 = 8 * fl2 * vv;                       // 4 r^2 phi^2 ll, r^2 <= 2 v + 2 es^2
+    const double C0 = 8 * fl2 * es * es + 1e-30;
+    // the kernel's FP32 evaluation of delta (seven roundings of positive
+    // terms) and ll against |l32|^2 (3.01 u) lose at most 16 u relative
+    const double f = M * (1.0 + 16 * u) / (1.0 - 2 * u);
+    a.dA0 = up32(f * A0);
+    a.dA1 = up32(f * A1);
+    a.dA2 = up32(f * A2);
+    a.dB0 = up32(f * B0);
+    a.dB1 = up32(f * B1);
+    a.dB2 = up32(f * B2);
+    a.dC2 = up32(f * C2);
+    a.dC0 = up32(f * C0);
+}
+
+// The mu decision of the z line of sight in mu space (linear mu edges
+// covering [0, 1]). The kernel forms ts2 = fl(|dz32| rsq(v) + s2) and
+// tq = fl(ts2 a + 1/2), the pair's position in bin units (edge j at j), and
+// takes bin floor(tq) when frac(tq) is at least beta from 0 and from 1.
+// With mu = |dz| / r exact, |dz32 - dz| <= ec, |v - r^2| <= D(r) (the d2
+// bound) and rsq within kRsqRel:
+//   |mu32 - mu| <= (1 + sqrt 3) ec / r + 1.5 ec^2 / r^2 + 1.51 u + kRsqRel
+// (mu32 = |dz32| rsq(v) exactly; 1/r <= rsq(v) (1 + kRsqRel) (1 + D / 2 r^2)).
+// A pair is certified only when beta < 1/2, i.e. ec / r < 1 / (8 a) here, so
+// the second-order terms are below 0.4 % of the first. In bin units,
+//   beta = a |mu32 - mu| + a u (1 + |s2|) + u (a + |b| + 1) + a |s2 - s2*|
+//          + dev + a E64 + 2 u,
+// with s2* the exact shift, dev the largest distance of the caller's edges
+// (in bin units) from the integers, E64 = 8 u64 the canonical FP64 mu
+// decision's own error, and 2 u for fl(frac - 1/2) and the FP32 fma of the
+// half-width. Kept as 1/2 - beta = muB1 rsq(v) + muB0, times a safety
+// factor 1.5 on beta.
+static void mu_space_band(const cute_binning* b, const ErrModel& em, Plan& pl) {
+    CountArgs& a = pl.a;
+    const int n2 = b->n2;
+    const double u = kU32, s3 = std::sqrt(3.0), ec = em.ec;
+    const double A = (double)a.e2a, B = (double)a.e2b, S2 = (double)a.s2;
+    double dev = 0.0;
+    for (int j = 0; j <= n2; j++)
+        dev = std::max(dev, std::fabs(b->edges2[j] * A + B - (double)j));
+    dev = dev * (1.0 + 1e-9) + 1e-12;
+    const double s2x = (B - 0.5) / A;
+    const double M = 1.5;
+    const double c1 = M * A * ((1.0 + s3) * ec * 1.01 * (1.0 + kRsqRel) + kRsqRel * ec);
+    const double c0 = M * (A * (1.51 * u * 1.01 + kRsqRel + u * (1.0 + std::fabs(S2)) * 1.01 +
+                                std::fabs(S2 - s2x) + 8.0 * kU64) +
+                           u * (A + std::fabs(B) + 1.0) + dev) +
+                      2.0 * u;
+    a.muB1 = -up32(c1);
+    a.muB0 = dn32(0.5 - c0);
+    pl.est |= E_MUF;
+}
+
 // FP32 rounding bands of the decision thresholds under the error model em.
 void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
     CountArgs& a = pl.a;
@@ -416,40 +556,9 @@ void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
             a.dA0p = up32(A0 - A1 * (double)a.s1 + 2.0 * kU32 * A1 * std::fabs((double)a.s1));
         else
             a.dA0p = up32(A0);
+        if (!a.d2_generic && !a.d2_partial) mu_space_band(b, em, pl);
     } else if (pl.mode == M_RMU_MID || pl.mode == M_SIGMAPI) {
-        // midpoint line of sight: perturbations of s = p - q (per component
-        // <= ec) and l = p + q (per component <= el) move the ratio predicates
-        // by first-order terms ~ r |s-error| ll and r^2 |l| |l-error|
-        const double es = s3 * ec, esl = s3 * em.el;
-        const double es64 = s3 * ec64, el64 = s3 * em.el64;
-        auto fill = [&](double c_lin, double c_round, double kmax2, float* A0, float* A1, float* A2,
-                        float* B0, float* B1, float* B2, float* C2, float* C0) {
-            // c_lin: multiplier of the first-order terms (4 for mu and sigma, 2 for pi)
-            double a1 = c_lin * (es + es64);
-            double a2 = c_round * (kU32 + kU64);
-            double a0 = 5 * (kU32 + kU64) * kmax2 + 6 * es * es + a1 * s3 * ec + a2 * 3 * ec * ec;
-            double b2 = c_lin * (esl + el64) + 2 * esl * a2;
-            double b1 = 2 * esl * a1 + c_lin * esl * 3.47 * ec + 4 * es * esl;
-            double b0 = 2 * (esl + el64) * kmax2 + 2 * esl * a0 + c_lin * esl * 3 * ec * ec;
-            double c2 = 12 * esl * esl + esl * esl * a2;
-            double c0 = 2 * kmax2 * esl * esl + esl * esl * a0;
-            const double f = 2.0;
-            *A0 = (float)(f * a0);
-            *A1 = (float)(f * a1);
-            *A2 = (float)(f * a2);
-            *B0 = (float)(f * b0);
-            *B1 = (float)(f * b1);
-            *B2 = (float)(f * b2);
-            *C2 = (float)(f * c2);
-            *C0 = (float)(f * c0);
-        };
-        if (b->kind == CUTE_BIN_SIGMAPI) {
-            const double smax2 = pl.T1[n1], pmax2 = pl.T2[b->n2];
-            fill(4.0, 15.5, smax2, &a.sA0, &a.sA1, &a.sA2, &a.sB0, &a.sB1, &a.sB2, &a.sC2, &a.sC0);
-            fill(2.0, 8.2, pmax2, &a.dA0, &a.dA1, &a.dA2, &a.dB0, &a.dB1, &a.dB2, &a.dC2, &a.dC0);
-        } else {
-            fill(4.0, 17.5, 1.0, &a.dA0, &a.dA1, &a.dA2, &a.dB0, &a.dB1, &a.dB2, &a.dC2, &a.dC0);
-        }
+        midpoint_bands(b, em, pl);
     }
 }
 

@@ -19,16 +19,23 @@ cute_status hip_status(hipError_t e, const char* what);
         if (e__ != hipSuccess) return ::cute::hip_status(e__, #call);   \
     } while (0)
 
-// Make the default memory pool keep freed blocks (stream-ordered reuse).
+// Set up the library's memory pool on the current device (once per device).
 cute_status ensure_device_ready(int* device);
+
+// Stream-ordered device allocation from the library's own pool (its freed
+// blocks are kept for reuse up to a bound, without changing the device's
+// default pool for the rest of the process). Every device allocation of the
+// library goes through here, so that a test can make the n-th one fail: while
+// the environment sets CUTE_TEST_FAIL_ALLOC=n (n > 0), every n-th call
+// reports CUTE_E_OUT_OF_MEMORY instead of allocating.
+cute_status dev_malloc_async(void** p, size_t bytes, hipStream_t s);
+bool inject_alloc_failure();
 
 template <typename T>
 cute_status dalloc(T** p, size_t count, hipStream_t s) {
     *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), count * sizeof(T), s);
-    if (e != hipSuccess) return hip_status(e, "hipMallocAsync");
-    return CUTE_OK;
+    return dev_malloc_async(reinterpret_cast<void**>(p), count * sizeof(T), s);
 }
 
 inline void dfree(void* p, hipStream_t s) {

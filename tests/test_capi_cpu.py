@@ -215,3 +215,35 @@ def test_jackknife_cross_rejects_bad_arguments(lib):
         assert lib.cute_count_jackknife_cross(
             ga, None if ra is None else ra.ctypes.data, gb, None if rb is None else rb.ctypes.data,
             0, k, ctypes.byref(b), 1, out.ctypes.data, out.ctypes.data, None, None) == cute.E_INVALID_ARG
+
+
+def test_xi_estimate_exact_arithmetic_guard(lib):
+    """The 128-bit exact Landy-Szalay evaluation accepts catalogs below 2^31
+    points with counts up to their pair totals (the largest values give the
+    exact closed form) and rejects anything larger instead of overflowing."""
+    from fractions import Fraction
+    good = cute.Binning(cute.BIN_MONO, [0.0, 1.0])
+    xi = np.zeros(1)
+    pxi = xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    n = (1 << 31) - 1
+    top = n * (n - 1) // 2
+    dd = np.array([top], dtype=np.uint64)
+    dr = np.array([n * n], dtype=np.uint64)
+    rr = np.array([top], dtype=np.uint64)
+    assert lib.cute_xi_estimate(cute.EST_LS, dd.ctypes.data, dr.ctypes.data, rr.ctypes.data, n, n,
+                                ctypes.byref(good.c()), 0.0, pxi) == cute.OK
+    num = n * (n - 1) * top - (n - 1) * (n - 1) * (n * n) + n * (n - 1) * top
+    assert xi[0] == float(Fraction(num, n * (n - 1) * top))
+    # sizes at 2^31 and counts above their pair totals are refused
+    for nd, nr in ((1 << 31, 10), (10, 1 << 31)):
+        small = np.array([1], dtype=np.uint64)
+        assert lib.cute_xi_estimate(cute.EST_LS, small.ctypes.data, small.ctypes.data,
+                                    small.ctypes.data, nd, nr, ctypes.byref(good.c()), 0.0,
+                                    pxi) == cute.E_INVALID_ARG
+    for name in ("dd", "dr", "rr"):
+        c = {"dd": np.array([45], dtype=np.uint64), "dr": np.array([100], dtype=np.uint64),
+             "rr": np.array([45], dtype=np.uint64)}
+        c[name] = c[name] + np.uint64(1)
+        assert lib.cute_xi_estimate(cute.EST_LS, c["dd"].ctypes.data, c["dr"].ctypes.data,
+                                    c["rr"].ctypes.data, 10, 10, ctypes.byref(good.c()), 0.0,
+                                    pxi) == cute.E_INVALID_ARG, name

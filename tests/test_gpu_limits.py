@@ -170,3 +170,40 @@ def test_top_edge_skip_is_exact(kind):
         say("top-edge skip, %s, prec %d" % (kind, prec))
         np.testing.assert_array_equal(cute.count_pairs(ga, None, bn, prec), want_aa)
         np.testing.assert_array_equal(cute.count_pairs(ga, gb, bn, prec), want_ab)
+
+
+def test_allocation_failures_are_reported_and_recovered():
+    """The allocation-failure hook (CUTE_TEST_FAIL_ALLOC=n: while set, every
+    n-th device allocation of the library reports out-of-memory): grid
+    builds, single counts and batches return CUTE_E_OUT_OF_MEMORY at every
+    allocation they make, release what they had, and the same calls succeed
+    once the hook is cleared, with the oracle's counts."""
+    import os
+    a = catalogs.uniform_box(3000, 200.0, seed=811)
+    e = np.linspace(0.0, 30.0, 7)
+    bn = cute.Binning(cute.BIN_MONO, e)
+    want = oracle.count_pairs(a, None, oracle.Binning(oracle.MONO, e))
+    g = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=30.0)
+    seen = set()
+    try:
+        for n in (1, 2, 3, 5, 8):
+            os.environ["CUTE_TEST_FAIL_ALLOC"] = str(n)
+            say("allocation failure every %d-th allocation" % n)
+            for call in ("grid", "count", "batch"):
+                try:
+                    if call == "grid":
+                        cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=30.0).close()
+                    elif call == "count":
+                        cute.count_pairs(g, None, bn, cute.PREC_FP32_EDGE)
+                    else:
+                        cute.count_pairs_batched([cute.BatchItem(g, None, bn)], cute.PREC_FP32_EDGE)
+                except cute.CuteError as err:
+                    assert err.status == cute.E_OUT_OF_MEMORY, str(err)
+                    seen.add(call)
+    finally:
+        del os.environ["CUTE_TEST_FAIL_ALLOC"]
+    assert seen == {"grid", "count", "batch"}
+    for prec in EXACT:
+        np.testing.assert_array_equal(cute.count_pairs(g, None, bn, prec), want)
+    g2 = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=30.0)
+    np.testing.assert_array_equal(cute.count_pairs_batched([cute.BatchItem(g2, None, bn)])[0], want)

@@ -225,6 +225,17 @@ def make_angular_cap_1e7_rows():
     }
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 MAKERS = {"periodic_2e4_dd_mono": make_periodic_2e4_dd_mono,
           "clustered_1e6_dd_rmu": make_clustered_1e6_dd_rmu,
           "clustered_1e6_dr_rmu": make_clustered_1e6_dr_rmu,
@@ -242,6 +253,8 @@ if __name__ == "__main__":
         rec = MAKERS[name]()
         rec["source"] = ("computed by tests/golden/make_golden.py with the CPU oracle "
                          "(oracle/oracle.c); no GPU value was used")
+        rec["threads"] = os.cpu_count()
+        rec["host"] = cpu_model()
         with open(os.path.join(HERE, name + ".json"), "w") as f:
             json.dump(rec, f)
         print(name, "done in %.1f s" % rec["oracle_seconds"], flush=True)

@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_LANE_OPS = 256 * 64 * 2.4e9     # unpacked VALU lane-instructions/s (256 CUs, 2.4 GHz)
+PEAK_FP32_FLOPS = 157.3e12            # FP32 vector peak (packed FMA counted as 4 flops per lane)
 I_ALG_RMU_Z = 21                      # algorithmic FP32 lane-ops per r-mu pair evaluation
 
 
@@ -33,15 +34,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """Host CPU model and core counts (the oracle's timing context)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": affinity,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(d, target_s=15.0):
     """The CPU oracle (brute force, every pair) on a bounded prefix of the
-    same data catalog; its rate is reported in the same unit."""
+    same data catalog, on every core this process may use (the job's CPU
+    share: OMP_NUM_THREADS when set, else the affinity mask), and once on one
+    thread; rates in the same unit. The pruned oracle time to solution of
+    the whole workload comes from the golden record (measured when the
+    expected counts were made)."""
     import oracle
-    try:
-        threads = len(os.sched_getaffinity(0))
-    except Exception:
-        threads = os.cpu_count() or 1
-    threads = max(1, min(threads, 16))
+    info = host_info()
+    threads = int(info["omp_num_threads"] or 0) or info["affinity_cores"]
+    threads = max(1, threads)
     re_, me = np.arange(41) * 5.0, np.arange(51) / 50.0
     ob = oracle.Binning(oracle.RMU, re_, me, los=oracle.LOS_Z)
     n = 20000
@@ -54,9 +76,26 @@ def cpu_baseline(d, target_s=15.0):
     oracle.count_pairs(d.head(n2), None, ob, nthreads=threads)
     dt = time.perf_counter() - t
     pairs = n2 * (n2 - 1) / 2
-    return {"value": pairs / dt / 1e9, "unit": "Gpair-evals/s", "cores": threads, "kind": "oracle",
-            "sample": "brute-force DD (all %d pairs) of the first %d points of the same clustered "
-                      "catalog, same r-mu binning, %.1f s" % (pairs, n2, dt)}
+    # one thread, about 4 s of work
+    n1 = int(min(len(d), math.sqrt(2 * rate / threads * 4.0)))
+    t = time.perf_counter()
+    oracle.count_pairs(d.head(n1), None, ob, nthreads=1)
+    dt1 = time.perf_counter() - t
+    out = {"value": pairs / dt / 1e9, "unit": "Gpair-evals/s", "cores": threads, "kind": "oracle",
+           "sample": "brute-force DD (all %d pairs) of the first %d points of the same clustered "
+                     "catalog, same r-mu binning, %.1f s" % (pairs, n2, dt),
+           "single_thread": {"value": n1 * (n1 - 1) / 2 / dt1 / 1e9, "unit": "Gpair-evals/s",
+                             "sample": "first %d points, %.1f s" % (n1, dt1)},
+           "host": info}
+    golden = os.path.join(ROOT, "tests", "golden", "clustered_1e6_dd_rmu.json")
+    if os.path.exists(golden):
+        with open(golden) as f:
+            g = json.load(f)
+        out["pruned_time_to_solution_s"] = {
+            "value": round(g["oracle_seconds"], 1),
+            "what": "the whole DD of the 1e6-point workload with the exact band-and-window prune",
+            "threads": g.get("threads", 8), "where": g.get("host", "the build container")}
+    return out
 
 
 def batched_leg(cute, torch, dev, runs=1):
@@ -444,7 +483,7 @@ def main():
         "tiles_per_step": int(st32[-1]["tiles"]),
         "pairs_in_range_per_step": in_range,
         "retests_per_step": int(st32[-1]["retests"]),
-        "fp32_only_miscounts_per_step": int(st32[-1]["flips"]),
+        "flips_per_step": int(st32[-1]["flips"]),
         "pairs_in_range_per_s": in_range / (ms32 * 1e-3),
         "brute_force_equiv_pairs_per_s": n * (n - 1) / 2 / (ms32 * 1e-3),
         "fp64": {"ms_per_step": round(ms64, 4), "kernel_ms": round(kern64_ms, 4),
@@ -454,7 +493,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                      "unit": "Tlane-op/s", "frac": round(achieved / peak, 4),
                      "traffic": committed_traffic(),
-                     "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z},
+                     "traffic_source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel "
+                                       "source (profiles/k_count_rmu_clustered_1e6_dd.json), "
+                                       "not measured in this run; null when the source changed",
+                     "kernel_ms": round(kern_ms, 4), "i_alg": I_ALG_RMU_Z,
+                     "flop_convention_frac": round(evals * I_ALG_RMU_Z / (kern_ms * 1e-3)
+                                                   / PEAK_FP32_FLOPS, 4),
+                     "flop_convention_peak_tflops": PEAK_FP32_FLOPS / 1e12},
+        "fp32_only": fp32_only_leg(cute, xyz, bn, counts, c64, st32[-1]),
     }
     if not args.no_xi:
         log("bench: full xi(r, mu): DD, DR, RR, Landy-Szalay, multipoles")
@@ -471,6 +517,27 @@ def main():
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
+
+
+def fp32_only_leg(cute, xyz, bn, counts, c_exact, st_edge, reps=3):
+    """The FP32 fast path alone (no FP64 re-test) on the benchmark workload:
+    its kernel time and how far its counts are from the exact ones (the L1
+    distance of the histograms), beside the flips of the exact path (re-tested
+    pairs whose FP32-only decision was wrong)."""
+    g = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0)
+    best = None
+    for _ in range(reps):
+        _, st = cute.count_pairs(g, None, bn, cute.PREC_FP32_ONLY, out=counts, with_stats=True)
+        best = st["ms_count"] if best is None else min(best, st["ms_count"])
+    c = counts.cpu().numpy().astype(np.int64)
+    g.close()
+    l1 = int(np.abs(c - c_exact.astype(np.int64)).sum())
+    pir = int(c_exact.sum())
+    return {"kernel_ms": round(best, 4), "hist_l1_vs_exact": l1,
+            "hist_l1_per_pair_in_range": l1 / max(pir, 1),
+            "flips": int(st_edge["flips"]), "flips_per_pair_in_range": int(st_edge["flips"]) / max(pir, 1),
+            "note": "flips: re-tested pairs whose FP32-only decision differed from FP64 (FP32_EDGE "
+                    "run); hist_l1: sum over bins of |FP32_ONLY count - exact count|"}
 
 
 def xi_leg(cute, torch, dev, xyz, bn, c_dd, reps=3):

@@ -380,6 +380,10 @@ def main():
                     help="cell side of the grid (0 = the library's choice)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the sigma-pi and theta DD legs")
+    ap.add_argument("--only", choices=("sigmapi", "theta"), default=None,
+                    help="run only that DD leg and print its result (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -396,6 +400,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
+    if args.only:
+        print(json.dumps({args.only: mode_leg(cute, torch, dev, args.only)}), flush=True)
+        return
     d, _ = catalogs.clustered_box_1e6()
     n = len(d)
     xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (d.x, d.y, d.z)]
@@ -508,6 +515,9 @@ def main():
     # the cell-size tuner on the same data: its choice and the count time with it
     if not args.no_tune:
         out["tuned_cell"] = tuned_leg(cute, xyz, bn, counts, c32)
+    if not args.no_modes:
+        out["sigmapi_dd"] = mode_leg(cute, torch, dev, "sigmapi")
+        out["theta_dd"] = mode_leg(cute, torch, dev, "theta")
     if not args.no_batched:
         out["batched"] = batched_leg(cute, torch, dev)
     if not args.no_table2:
@@ -517,6 +527,72 @@ def main():
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
+
+
+I_ALG_SIGMAPI = 40                    # algorithmic FP32 lane-ops per sigma-pi (midpoint) pair evaluation
+I_ALG_THETA = 16                      # algorithmic FP32 lane-ops per theta pair evaluation
+
+
+def mode_leg(cute, torch, dev, kind, reps=2):
+    """The DD count of one more workload at full size, FP32_EDGE, FP64 and
+    FP32_ONLY kernels: 'sigmapi', the light cone (3e6 points, sigma and pi in
+    [0, 150) with 75 x 75 bins, midpoint line of sight), or 'theta', the
+    angular cap (1e7 clustered unit vectors, 30 log bins of theta in
+    [0.001, 10] deg). FP32_EDGE must equal FP64 (and the oracle's golden
+    counts where they exist); the VALU fraction is taken at the mode's
+    algorithmic lane-ops per pair."""
+    import catalogs
+    t0 = time.perf_counter()
+    if kind == "sigmapi":
+        cat, _ = catalogs.lightcone_3e6()
+        e = np.arange(76) * 2.0
+        bn = cute.Binning(cute.BIN_SIGMAPI, e, e, los=cute.LOS_MIDPOINT)
+        geom, reach, i_alg = cute.GEOM_BOX_OPEN, float(np.hypot(e[-1], e[-1])) * (1 + 1e-12), I_ALG_SIGMAPI
+        golden, workload = "lightcone_3e6_dd_sigmapi.json", (
+            "sigma-pi DD of the light cone: 3e6 points, RA 0-60 deg, Dec 0-30 deg, Gaussian n(z), "
+            "sigma and pi in [0, 150) Mpc/h, 75 x 75 bins, midpoint line of sight")
+    else:
+        cat, _ = catalogs.angular_cap_1e7()
+        e = np.deg2rad(0.001 * 10.0 ** (np.arange(31) * 4.0 / 30.0))
+        bn = cute.Binning(cute.BIN_THETA, e)
+        geom, reach, i_alg = cute.GEOM_SPHERE, float(e[-1]), I_ALG_THETA
+        golden, workload = None, ("theta DD of the angular cap: 1e7 clustered unit vectors in "
+                                  "5000 sq-deg, 30 log bins of theta in [0.001, 10] deg")
+    xyz = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (cat.x, cat.y, cat.z)]
+    g = cute.build_grid(xyz, geom, r_max=reach)
+    t_gen = time.perf_counter() - t0
+    res = {}
+    for name, prec in (("fp32_edge", cute.PREC_FP32_EDGE), ("fp64", cute.PREC_FP64),
+                       ("fp32_only", cute.PREC_FP32_ONLY)):
+        best = None
+        for _ in range(reps if name != "fp64" else 1):
+            c, st = cute.count_pairs(g, None, bn, prec, with_stats=True)
+            if best is None or st["ms_count"] < best[1]["ms_count"]:
+                best = (c, st)
+        res[name] = best
+        log("bench: %s DD %s %.1f ms" % (kind, name, best[1]["ms_count"]))
+    g.close()
+    c32, st = res["fp32_edge"]
+    exact = bool(np.array_equal(c32, res["fp64"][0]))
+    checked = "GPU FP64 path"
+    if golden is not None and os.path.exists(os.path.join(ROOT, "tests", "golden", golden)):
+        with open(os.path.join(ROOT, "tests", "golden", golden)) as f:
+            gr = json.load(f)
+        if gr["sha256_data"] == catalogs.sha256_of(cat):
+            exact = exact and bool(np.array_equal(c32.reshape(-1), np.array(gr["counts"], dtype=np.uint64)))
+            checked = "oracle golden counts"
+    ms = st["ms_count"]
+    pir = int(st["pairs_in_range"])
+    l1 = int(np.abs(res["fp32_only"][0].astype(np.int64) - c32.astype(np.int64)).sum())
+    return {"workload": workload, "bit_exact": exact, "checked_against": checked,
+            "kernel_ms": {k: round(v[1]["ms_count"], 3) for k, v in res.items()},
+            "pair_evals": int(st["pair_evals"]), "pairs_in_range": pir,
+            "retests": int(st["retests"]), "retests_per_pair_in_range": st["retests"] / max(pir, 1),
+            "fp32_only_hist_l1": l1, "flips": int(st["flips"]),
+            "gpair_evals_per_s": round(st["pair_evals"] / (ms * 1e-3) / 1e9, 1),
+            "speedup_fp32edge_vs_fp64": round(res["fp64"][1]["ms_count"] / ms, 3),
+            "valu_frac": round(st["pair_evals"] * i_alg / (ms * 1e-3) / PEAK_LANE_OPS, 4),
+            "i_alg": i_alg, "host_s": round(t_gen, 1)}
 
 
 def fp32_only_leg(cute, xyz, bn, counts, c_exact, st_edge, reps=3):

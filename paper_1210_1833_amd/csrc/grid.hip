@@ -122,17 +122,35 @@ __device__ inline uint32_t cell_of(const CellGeo& g, double x, double y, double 
     return (uint32_t)ix + (uint32_t)g.nx * ((uint32_t)iy + (uint32_t)g.ny * (uint32_t)iz);
 }
 
+// Points per thread of the key and scatter kernels: the rank of a point in
+// its cell is a returning atomic on the cell's counter, whose round trip
+// dominates; kPer independent ones per thread keep more of them in flight.
+constexpr int kPer = 4;
+
 __global__ __launch_bounds__(kBlock) void k_cell_keys(const double* __restrict__ x,
                                                       const double* __restrict__ y,
                                                       const double* __restrict__ z, int64_t n,
                                                       CellGeo g, uint32_t* __restrict__ key,
                                                       uint32_t* __restrict__ rank,
                                                       uint32_t* __restrict__ count) {
-    int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c = cell_of(g, x[i], y[i], z[i]);
-    key[i] = c;
-    rank[i] = atomicAdd(&count[c], 1u);
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * kPer) + threadIdx.x;
+    uint32_t c[kPer], r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        c[k] = i < n ? cell_of(g, x[i], y[i], z[i]) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; k++)
+        if (base + (int64_t)k * kBlock < n) r[k] = atomicAdd(&count[c[k]], 1u);
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        if (i < n) {
+            key[i] = c[k];
+            rank[i] = r[k];
+        }
+    }
 }
 
 // Exclusive scan, three phases: per-block scan of kScanItems items, scan of
@@ -188,18 +206,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
     int64_t n, const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
     const uint32_t* __restrict__ cstart, double cx, double cy, double cz,
     float4* __restrict__ p32, P64* __restrict__ p64) {
-    int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (i >= n) return;
-    uint32_t pos = cstart[key[i]] + rank[i];
-    double a = x[i], b = y[i], c = z[i];
-    p32[pos] = make_float4((float)(a - cx), (float)(b - cy), (float)(c - cz), 0.0f);
-    P64 q;
-    q.x = a;
-    q.y = b;
-    q.z = c;
-    q.idx = (uint32_t)i;
-    q.pad = 0u;
-    p64[pos] = q;
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * kPer) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        if (i >= n) break;
+        uint32_t pos = cstart[key[i]] + rank[i];
+        double a = x[i], b = y[i], c = z[i];
+        p32[pos] = make_float4((float)(a - cx), (float)(b - cy), (float)(c - cz), 0.0f);
+        P64 q;
+        q.x = a;
+        q.y = b;
+        q.z = c;
+        q.idx = (uint32_t)i;
+        q.pad = 0u;
+        p64[pos] = q;
+    }
 }
 
 }  // namespace
@@ -444,7 +466,7 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
     if ((st = zero_u32(g.cstart, (size_t)ncells + 1, s)) != CUTE_OK) return cleanup(st);
     CellGeo cg{(int)g.geom, g.nx, g.ny, g.nz, g.ox, g.oy, g.oz, g.ax, g.ay, g.az, g.L};
     if (n > 0) {
-        unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+        unsigned nb = (unsigned)((n + kBlock * kPer - 1) / (kBlock * kPer));
         hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(kBlock), 0, s, dx, dy, dz, n, cg, key, rank,
                            g.cstart);
         if (hipGetLastError() != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "cell keys launch"));
@@ -452,7 +474,7 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
     if ((st = exclusive_scan(g.cstart, g.cstart, (size_t)ncells + 1, s)) != CUTE_OK)
         return cleanup(st);
     if (n > 0) {
-        unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+        unsigned nb = (unsigned)((n + kBlock * kPer - 1) / (kBlock * kPer));
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, dx, dy, dz, n, key, rank,
                            g.cstart, g.cx, g.cy, g.cz, g.p32, g.p64);
         if (hipGetLastError() != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "scatter launch"));

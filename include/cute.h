@@ -37,7 +37,10 @@
  *  - All device work of a call is issued on the given stream (NULL = the
  *    null stream) and the call returns after that work has finished, except
  *    cute_batch_run, which only enqueues (and copies to device memory, which
- *    stay ordered on the stream).
+ *    stay ordered on the stream), and cute_build_grid, which returns once the
+ *    build is enqueued: every later call that takes the grid, on any stream,
+ *    orders its device work after the build (a device-side wait, no host
+ *    wait), and cute_get_grid_info waits for the build to report its time.
  */
 #ifndef CUTE_H
 #define CUTE_H
@@ -146,6 +149,10 @@ typedef struct cute_grid cute_grid;
  * of the sphere) are assigned, the points are sorted by cell, and sorted
  * FP64 and origin-shifted FP32 copies plus cell offsets are kept on the
  * device. x, y, z: n float64 each (host, or device if p->device_ptrs).
+ * The call waits once, for the bounding box and the input checks (host
+ * inputs are copied by then); the rest of the build runs on `stream` after
+ * it returns, so device inputs must stay valid until work that follows the
+ * build on `stream` (or any call that takes the grid) has finished.
  * n may be 0. *out receives a new grid on success (free with cute_free_grid).
  * Errors: CUTE_E_INVALID_ARG for NULL pointers, n < 0 or n >= 2^31,
  * non-finite coordinates, periodic coordinates outside [0, L), vectors that

@@ -133,6 +133,13 @@ cute_status create(const cute_batch_item* items, int32_t n_items, cute_precision
     // ---- bands (one error model per group), LDS plan, kernel attributes -----
     int dev = 0, ncu = 0;
     if ((s = ensure_device_ready(&dev)) != CUTE_OK) return s;
+    // the set-up work on hs (and every replay, which follows it) comes after
+    // the builds of the grids
+    for (int i = 0; i < n_items; i++) {
+        if ((s = grid_wait(items[i].a, hs)) != CUTE_OK) return s;
+        if (items[i].b && items[i].b != items[i].a && (s = grid_wait(items[i].b, hs)) != CUTE_OK)
+            return s;
+    }
     b->device = dev;
     CUTE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     for (Group& G : b->groups) {

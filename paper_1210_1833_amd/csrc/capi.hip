@@ -208,6 +208,12 @@ cute_status count_impl(const cute_grid* ga, const cute_grid* gb, const cute_binn
     if (!gb) gb = ga;
     const GridHost& A = ga->h;
     const GridHost& B = gb->h;
+    {
+        // work on this stream follows the builds of both grids
+        cute_status w;
+        if ((w = grid_wait(ga, (hipStream_t)stream)) != CUTE_OK) return w;
+        if (gb != ga && (w = grid_wait(gb, (hipStream_t)stream)) != CUTE_OK) return w;
+    }
     const bool weighted = A.wt != nullptr || B.wt != nullptr;
     if (weighted && (A.wt == nullptr || B.wt == nullptr))
         return fail(CUTE_E_INVALID_ARG, "a pixel map pairs only with another pixel map");

@@ -201,9 +201,16 @@ struct GridHost {
     uint32_t* pix_n;
     void* wblock;
     int n_cth, n_phi;
-    double ms_build;
+    // the build's start and end on its stream: work that uses the grid on any
+    // stream waits for ev_ready on the device; the build time is read from
+    // the pair when asked (nullptr when the build finished before returning)
+    hipEvent_t ev_start, ev_ready;
+    double ms_build;     // the build time when known without a wait (< 0: ask the events)
     GridView view() const;
 };
+
+// Make later work on stream s wait (on the device) for the build of g.
+cute_status grid_wait(const cute_grid* g, hipStream_t s);
 
 // Inputs of the FP32 rounding-error bounds (absolute errors per component).
 struct ErrModel {

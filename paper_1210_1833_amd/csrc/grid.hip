@@ -479,20 +479,40 @@ extern "C" cute_status cute_build_grid(const double* x, const double* y, const d
                            g.cstart, g.cx, g.cy, g.cz, g.p32, g.p64);
         if (hipGetLastError() != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "scatter launch"));
     }
-    // the end event follows the last kernel: waiting for it waits for the build
+    // the end event follows the last kernel; the grid keeps both events, and
+    // work that uses it (on any stream) waits for the end on the device, so
+    // the call returns without waiting (the host inputs were copied before
+    // the statistics read-back above)
     timer.stop();
-    const hipError_t we = timer.b ? hipEventSynchronize(timer.b) : hipStreamSynchronize(s);
-    if (we != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "build sync"));
-    g.ms_build = timer.elapsed_ms();
+    if (timer.a && timer.b) {
+        g.ev_start = timer.a;
+        g.ev_ready = timer.b;
+        timer.a = timer.b = nullptr;   // owned by the grid from here on
+        g.ms_build = -1.0;
+    } else {
+        if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(CUTE_E_DEVICE, "build sync"));
+        g.ms_build = 0.0;
+    }
     grid->h = g;
     *out = grid;
+    return CUTE_OK;
+}
+
+cute_status cute::grid_wait(const cute_grid* g, hipStream_t s) {
+    if (g && g->h.ev_ready) CUTE_HIP(hipStreamWaitEvent(s, g->h.ev_ready, 0));
     return CUTE_OK;
 }
 
 extern "C" void cute_free_grid(cute_grid* g) {
     if (!g) return;
     // the buffers come from the stream-ordered pool; the caller guarantees
-    // that no work on any stream still uses the grid
+    // that no work on any stream still uses the grid, and the build itself is
+    // waited for (in practice long finished: any count of the grid returned)
+    if (g->h.ev_ready) {
+        (void)hipEventSynchronize(g->h.ev_ready);
+        (void)hipEventDestroy(g->h.ev_ready);
+    }
+    if (g->h.ev_start) (void)hipEventDestroy(g->h.ev_start);
     dfree(g->h.block, nullptr);
     dfree(g->h.wblock, nullptr);
     delete g;
@@ -511,5 +531,12 @@ extern "C" cute_status cute_get_grid_info(const cute_grid* g, cute_grid_info* in
     info->origin[1] = g->h.oy;
     info->origin[2] = g->h.oz;
     info->ms_build = g->h.ms_build;
+    if (g->h.ev_ready) {
+        // the build time: wait for its end event
+        CUTE_HIP(hipEventSynchronize(g->h.ev_ready));
+        float ms = 0.f;
+        if (g->h.ev_start) CUTE_HIP(hipEventElapsedTime(&ms, g->h.ev_start, g->h.ev_ready));
+        info->ms_build = ms;
+    }
     return CUTE_OK;
 }

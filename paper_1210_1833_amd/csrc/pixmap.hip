@@ -266,6 +266,10 @@ extern "C" cute_status cute_build_pixel_map(const double* x, const double* y, co
         return fail(CUTE_E_DEVICE, "pixel map sync");
     }
     G.ms_build = timer.elapsed_ms();
+    // the whole map is built: its time replaces that of the centres' grid
+    if (G.ev_ready) (void)hipEventDestroy(G.ev_ready);
+    if (G.ev_start) (void)hipEventDestroy(G.ev_start);
+    G.ev_ready = G.ev_start = nullptr;
     *out = g;
     return CUTE_OK;
 }
@@ -276,6 +280,8 @@ extern "C" cute_status cute_pixel_map_read(const cute_grid* g, uint32_t* ids, ui
     const GridHost& G = g->h;
     if (G.wt == nullptr) return fail(CUTE_E_INVALID_ARG, "not a pixel map");
     hipStream_t s = (hipStream_t)stream;
+    cute_status st = grid_wait(g, s);
+    if (st != CUTE_OK) return st;
     if (G.n > 0 && ids)
         CUTE_HIP(hipMemcpyAsync(ids, G.pix_id, G.n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     if (G.n > 0 && counts)

@@ -442,6 +442,24 @@ def main():
     dt64, st64 = run(cute.PREC_FP64, args.fp64_steps, 1)
     c64 = counts.cpu().numpy().astype(np.uint64)
 
+    # the grid build alone: host time of the call (it returns once the build
+    # is enqueued), the wall time of builds in a row, and the GPU time of one
+    # build from its events
+    nb_ = 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    host_ms, gpu_ms = [], []
+    for _ in range(nb_):
+        t1 = time.perf_counter()
+        g = cute.build_grid(xyz, cute.GEOM_BOX_OPEN, r_max=200.0, cell_size=args.cell_size)
+        host_ms.append((time.perf_counter() - t1) * 1e3)
+        gpu_ms.append(g.info().ms_build)
+        g.close()
+    torch.cuda.synchronize()
+    build = {"calls": nb_, "ms_wall_per_build": round((time.perf_counter() - t0) / nb_ * 1e3, 4),
+             "ms_host_call": round(float(np.median(host_ms)), 4),
+             "ms_gpu_build": round(float(np.median(gpu_ms)), 4)}
+
     exact = bool(np.array_equal(c32, c64))
     golden = os.path.join(ROOT, "tests", "golden", "clustered_1e6_dd_rmu.json")
     oracle_checked = False
@@ -493,6 +511,8 @@ def main():
         "flips_per_step": int(st32[-1]["flips"]),
         "pairs_in_range_per_s": in_range / (ms32 * 1e-3),
         "brute_force_equiv_pairs_per_s": n * (n - 1) / 2 / (ms32 * 1e-3),
+        "step_overhead_ms": round(ms32 - kern_ms, 4),
+        "grid_build": build,
         "fp64": {"ms_per_step": round(ms64, 4), "kernel_ms": round(kern64_ms, 4),
                  "gpair_evals_per_s": round(st64[-1]["pair_evals"] / (ms64 * 1e-3) / 1e9, 3)},
         "speedup_fp32edge_vs_fp64": round(ms64 / ms32, 3),

@@ -122,10 +122,21 @@ __device__ inline uint32_t cell_of(const CellGeo& g, double x, double y, double 
     return (uint32_t)ix + (uint32_t)g.nx * ((uint32_t)iy + (uint32_t)g.ny * (uint32_t)iz);
 }
 
-// Points per thread of the key and scatter kernels: the rank of a point in
-// its cell is a returning atomic on the cell's counter, whose round trip
-// dominates; kPer independent ones per thread keep more of them in flight.
+// Points per thread of the key and scatter kernels: kPer independent loads
+// and atomics per thread keep more of them in flight.
 constexpr int kPer = 4;
+
+// The rank of a point in its cell comes from a returning atomic on the cell's
+// counter. Clustered catalogs put many points in a few cells, and atomics on
+// one address serialise in L2, so a block first counts its own points per
+// cell in an LDS table (open addressing, twice as many slots as points, so
+// that probing always ends) and then takes one global atomic per distinct
+// cell for the base of its ranks.
+constexpr int kSlotBits = 11;
+constexpr int kSlots = 1 << kSlotBits;
+static_assert(kSlots >= 2 * kBlock * kPer, "the cell table must stay at most half full");
+static_assert(kSlots % kBlock == 0, "whole slots per thread");
+constexpr uint32_t kNoCell = 0xffffffffu;   // never a cell index (fewer than 2^26 cells)
 
 __global__ __launch_bounds__(kBlock) void k_cell_keys(const double* __restrict__ x,
                                                       const double* __restrict__ y,
@@ -133,22 +144,67 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(const double* __restrict__
                                                       CellGeo g, uint32_t* __restrict__ key,
                                                       uint32_t* __restrict__ rank,
                                                       uint32_t* __restrict__ count) {
+    __shared__ uint32_t tcell[kSlots];
+    __shared__ uint32_t tnum[kSlots];
+    for (int j = threadIdx.x; j < kSlots; j += kBlock) {
+        tcell[j] = kNoCell;
+        tnum[j] = 0u;
+    }
     const int64_t base = (int64_t)blockIdx.x * (kBlock * kPer) + threadIdx.x;
-    uint32_t c[kPer], r[kPer];
+    uint32_t c[kPer], slot[kPer], local[kPer];
+    double px[kPer], py[kPer], pz[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; k++) {
-        const int64_t i = base + (int64_t)k * kBlock;
-        c[k] = i < n ? cell_of(g, x[i], y[i], z[i]) : 0u;
+        // every load issued before the first use (a point past the end reads
+        // the last one, n > 0, and is dropped)
+        int64_t i = base + (int64_t)k * kBlock;
+        i = i < n ? i : n - 1;
+        px[k] = x[i];
+        py[k] = y[i];
+        pz[k] = z[i];
     }
 #pragma unroll
     for (int k = 0; k < kPer; k++)
-        if (base + (int64_t)k * kBlock < n) r[k] = atomicAdd(&count[c[k]], 1u);
+        c[k] = base + (int64_t)k * kBlock < n ? cell_of(g, px[k], py[k], pz[k]) : kNoCell;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        slot[k] = 0u;
+        local[k] = 0u;
+        if (c[k] == kNoCell) continue;
+        uint32_t h = (c[k] * 2654435761u) >> (32 - kSlotBits);
+        for (;;) {
+            const uint32_t old = atomicCAS(&tcell[h], kNoCell, c[k]);
+            if (old == kNoCell || old == c[k]) break;
+            h = (h + 1u) & (kSlots - 1);
+        }
+        slot[k] = h;
+        local[k] = atomicAdd(&tnum[h], 1u);
+    }
+    __syncthreads();
+    {
+        // one global atomic per distinct cell, all of a thread's in flight
+        // together; tnum then holds the block's base rank in each cell
+        constexpr int kSlotsPer = kSlots / kBlock;
+        uint32_t m[kSlotsPer], cc[kSlotsPer];
+#pragma unroll
+        for (int q = 0; q < kSlotsPer; q++) {
+            m[q] = tnum[threadIdx.x + q * kBlock];
+            cc[q] = tcell[threadIdx.x + q * kBlock];
+        }
+#pragma unroll
+        for (int q = 0; q < kSlotsPer; q++)
+            if (m[q]) m[q] = atomicAdd(&count[cc[q]], m[q]);
+#pragma unroll
+        for (int q = 0; q < kSlotsPer; q++) tnum[threadIdx.x + q * kBlock] = m[q];
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPer; k++) {
         const int64_t i = base + (int64_t)k * kBlock;
         if (i < n) {
             key[i] = c[k];
-            rank[i] = r[k];
+            rank[i] = tnum[slot[k]] + local[k];
         }
     }
 }
@@ -207,20 +263,35 @@ __global__ __launch_bounds__(kBlock) void k_scatter(
     const uint32_t* __restrict__ cstart, double cx, double cy, double cz,
     float4* __restrict__ p32, P64* __restrict__ p64) {
     const int64_t base = (int64_t)blockIdx.x * (kBlock * kPer) + threadIdx.x;
+    // all loads of the kPer points first, then the gathers of their cell
+    // starts, then the stores (a point past the end reads the last one,
+    // n > 0, and stores nothing)
+    uint32_t kk[kPer], rk[kPer], pos[kPer];
+    double a[kPer], b[kPer], c[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        int64_t i = base + (int64_t)k * kBlock;
+        i = i < n ? i : n - 1;
+        kk[k] = key[i];
+        rk[k] = rank[i];
+        a[k] = x[i];
+        b[k] = y[i];
+        c[k] = z[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; k++) pos[k] = cstart[kk[k]] + rk[k];
 #pragma unroll
     for (int k = 0; k < kPer; k++) {
         const int64_t i = base + (int64_t)k * kBlock;
         if (i >= n) break;
-        uint32_t pos = cstart[key[i]] + rank[i];
-        double a = x[i], b = y[i], c = z[i];
-        p32[pos] = make_float4((float)(a - cx), (float)(b - cy), (float)(c - cz), 0.0f);
+        p32[pos[k]] = make_float4((float)(a[k] - cx), (float)(b[k] - cy), (float)(c[k] - cz), 0.0f);
         P64 q;
-        q.x = a;
-        q.y = b;
-        q.z = c;
+        q.x = a[k];
+        q.y = b[k];
+        q.z = c[k];
         q.idx = (uint32_t)i;
         q.pad = 0u;
-        p64[pos] = q;
+        p64[pos[k]] = q;
     }
 }
 

@@ -22,19 +22,33 @@ typedef const __attribute__((address_space(4))) double* cdp;
 typedef const __attribute__((address_space(4))) uint32_t* cu32p;
 typedef const __attribute__((address_space(4))) double* cf64p;
 
-__device__ __forceinline__ float4 load_u32x4f(const float4* p, uint32_t j) {
-    const cfp f = (cfp)(const void*)p;
-    return make_float4(f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3]);
+// x, y, z of the U consecutive points h .. h+U-1 from one base address with
+// constant offsets (the index is widened before the offsets are added, so the
+// scalar loads share one address computation and can merge)
+template <uint32_t U>
+__device__ __forceinline__ void load_points32(const float4* p, uint32_t h, float* x, float* y,
+                                              float* z) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(4))) f4v* cf4p;
+    const cf4p f = (cf4p)(const void*)(p + h);
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        const f4v q = f[u];
+        x[u] = q.x;
+        y[u] = q.y;
+        z[u] = q.z;
+    }
 }
-__device__ __forceinline__ P64 load_u64x3(const P64* p, uint32_t j) {
-    const cdp f = (cdp)(const void*)p;
-    P64 q;
-    q.x = f[4 * j];
-    q.y = f[4 * j + 1];
-    q.z = f[4 * j + 2];
-    q.idx = 0u;
-    q.pad = 0u;
-    return q;
+template <uint32_t U>
+__device__ __forceinline__ void load_points64(const P64* p, uint32_t h, double* x, double* y,
+                                              double* z) {
+    const cdp f = (cdp)(const void*)(p + h);
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        x[u] = f[4 * u];
+        y[u] = f[4 * u + 1];
+        z[u] = f[4 * u + 2];
+    }
 }
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -587,13 +601,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
                                        float qlx, float qly, float qlz, uint32_t lb, uint32_t lw,
                                        uint32_t ts, uint64_t& ambh, uint64_t& hsum, uint32_t h) {
     float hx[U], hy[U], hz[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++) {
-        const float4 p = load_u32x4f(P.A.p32, h + u);
-        hx[u] = p.x;
-        hy[u] = p.y;
-        hz[u] = p.z;
-    }
+    load_points32<U>(P.A.p32, h, hx, hy, hz);
     bool hv[U];
     home_valid<PM, U>(P, h, hv);
     uint32_t hw[U];
@@ -685,13 +693,7 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
                                        uint32_t lj, double qx, double qy, double qz, double sx, double sy,
                                        double sz, uint32_t lw, uint32_t h, double qr) {
     double hx[U], hy[U], hz[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; u++) {
-        const P64 p = load_u64x3(P.A.p64, h + u);
-        hx[u] = p.x;
-        hy[u] = p.y;
-        hz[u] = p.z;
-    }
+    load_points64<U>(P.A.p64, h, hx, hy, hz);
     bool hv[U];
     home_valid<PM, U>(P, h, hv);
     uint32_t hw[U];

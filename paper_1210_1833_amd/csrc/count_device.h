@@ -262,6 +262,20 @@ __device__ __forceinline__ uint32_t est_bits(float ts, float a, const Tab32& T, 
     return med3u(__float_as_uint(fmaf(ts, a, __uint_as_float(T.vbias))), T.vbias, top);
 }
 
+// The same estimate in two parts: the float e = fl(2^23 + x), x = ts a, is
+// 2^23 + round(x) for x >= -1/4; its bits clamped to the bins (est_bits) are
+// those of the float 2^23 + k, k the pair's bin along that dimension. The
+// offset x - k is formed with one rounding (the fma adds 2^23 - (2^23 + k),
+// exact, to the exact product ts a): the pair's distance from the centre of
+// bin k in bin units, at least 1/2 in size for a pair outside bin k (past
+// the first or the last bin included).
+__device__ __forceinline__ float est_float(float ts, float a, const Tab32& T) {
+    return fmaf(ts, a, __uint_as_float(T.vbias));
+}
+__device__ __forceinline__ float est_offset(float ts, float a, const Tab32& T, uint32_t kbits) {
+    return fmaf(ts, a, __uint_as_float(T.vbias) - __uint_as_float(kbits));
+}
+
 __device__ __forceinline__ float2 band_at(uint32_t tb, uint32_t kb) {
     const f2v b = *(lds_f2p)(uintptr_t)((kb << 3) + tb);
     return make_float2(b.x, b.y);
@@ -301,22 +315,31 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
     if (MODE == M_RMU_Z) {
         float rinv = __builtin_amdgcn_rsqf(v);
         float ts = est_log(EST) ? __builtin_amdgcn_logf(v) + P.s1 : fmaf(v, rinv, P.s1);
-        c.kb = est_bits(ts, P.e1a, T, P.top1);
+        const float er = est_float(ts, P.e1a, T);
+        c.kb = med3u(__float_as_uint(er), T.vbias, P.top1);
         float ts2 = fmaf(fabsf(dz), rinv, P.s2);
-        c.kmb = est_bits(ts2, P.e2a, T, P.top2);
+        const float em = est_float(ts2, P.e2a, T);
+        c.kmb = med3u(__float_as_uint(em), T.vbias, P.top2);
         float dz2 = dz * dz;
-        float2 b = band_at(T.tb1, c.kb);
-        bool rin = (v >= b.x) & (v < b.y);
+        // linear r bins: r is decided in bin units as mu is, without the
+        // band table; a pair certified there lies inside the v-space band of
+        // its bin
+        constexpr bool kRx = est_muf(EST) && !est_log(EST) && !WANT_TENT;
+        bool rin;
+        if constexpr (kRx) {
+            rin = fabsf(est_offset(ts, P.e1a, T, c.kb)) <= P.rB0;
+        } else {
+            float2 b = band_at(T.tb1, c.kb);
+            rin = (v >= b.x) & (v < b.y);
+        }
         bool min_;
         if (est_muf(EST) && !WANT_TENT) {
-            // in mu space: tq = mu a + b is the pair's position in bin units
-            // (ts2 a = tq - 1/2); the pair is inside bin floor(tq) when the
-            // fraction of tq is at least beta(r) = muB0' + |muB1| / r from
-            // both edges (T.d0 = 1/2 - muB0', the band kept as a half-width)
-            float tq = fmaf(ts2, P.e2a, 0.5f);
-            float fr = __builtin_amdgcn_fractf(tq);
+            // in mu space: x = ts2 a = mu a + b - 1/2 is the pair's position
+            // in bin units, inside its bin when the offset from the bin's
+            // centre is at most 1/2 - beta(r), beta(r) = muB0' + |muB1| / r
+            // (T.d0 = 1/2 - muB0', the band kept as a half-width)
             float half = fmaf(P.muB1, rinv, T.d0);
-            min_ = fabsf(fr - 0.5f) <= half;
+            min_ = fabsf(est_offset(ts2, P.e2a, T, c.kmb)) <= half;
         } else {
             float2 m = band_at(T.tb2, c.kmb);
             // band of the mu predicates, linear in r: dA1 r + dA0. With linear
@@ -326,10 +349,10 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
             float fhi = fmaf(m.y, v, dz2);
             min_ = (flo >= delta) & (fhi <= -delta);
         }
-        c.in = rin & min_;
         // only r decides a clean "out"; a pair outside a partial mu range is
         // re-tested instead (never the case for mu in [0, 1])
         c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);
+        c.in = rin & min_;
         if (WANT_TENT) {
             bool rr = v >= P.bot32 & v < P.top32;
             bool mm = true;

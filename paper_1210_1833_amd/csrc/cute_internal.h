@@ -124,10 +124,14 @@ struct CountArgs {
     // constant term of the mu band of the z line of sight as the kernel uses
     // it (dA0 for log r bins, dA0 - dA1 s1 plus its rounding for linear ones)
     float dA0p;
-    // mu in mu space (E_MUF): a pair is inside its mu bin when the fraction
-    // f of its position in bin units satisfies |f - 1/2| <= muB1 / r + muB0
-    // (muB1 < 0: the band grows as the separation shrinks)
+    // mu in mu space (E_MUF): a pair is inside its mu bin when the offset d
+    // of its position in bin units from the nearest bin centre satisfies
+    // |d| <= muB1 / r + muB0 (muB1 < 0: the band grows as the separation
+    // shrinks)
     float muB1, muB0;
+    // r in bin units (E_MUF with linear r bins, which start at r = 0 then):
+    // inside its r bin when |d| <= rB0
+    float rB0;
     // precomputed neighbour rows (see ItemGeom::stencil), or nullptr
     const int4* stencil;
     int nst;

@@ -502,6 +502,46 @@ static void mu_space_band(const cute_binning* b, const ErrModel& em, Plan& pl) {
     pl.est |= E_MUF;
 }
 
+// r in bin units for the z line of sight with linear r bins (Sec. 2.1, r of
+// the pair). The kernel forms ts = fl(v rsq(v) + s1) and x = ts a (a, s1 the
+// FP32 map: bin k is x in [k - 1/2, k + 1/2)) and certifies the pair inside
+// its estimated bin k (clamped to the bins) when |x - k| <= 1/2 - beta; a
+// pair outside the bins has |x - k| >= 1/2. At an edge e_k, with ê_k =
+// sqrt(T1[k]) (T1[k] the canonical FP64 threshold):
+//  - x differs from a (sqrt(v) + s1) by the rsq error a sqrt(v) kRsqRel, the
+//    rounding of ts u a (sqrt(v) + |s1|) and the rounding of the offset;
+//  - the FP32 map puts the edge at a distance dev_k = |a (ê_k + s1) - (k -
+//    1/2)| from ê_k (in x);
+//  - a pair with x at least beta past the map's edge has sqrt(v) >= ê_k +
+//    delta, delta = (beta - err - dev_k) / a, so v >= T1[k] + 2 ê_k delta;
+//    delta >= m_k / (1.5 ê_k) puts v past the v-space band m_k of the edge
+//    (the band of the table path), on the side the canonical FP64 compare
+//    takes. Below an edge v <= T1[k] - 2 ê_k delta + delta^2, and delta is
+//    less than half a bin, at most ê_k / 2 for k >= 1 with e_0 = 0.
+// The edge e_0 = 0 cannot be crossed (r >= 0). beta is the largest of these
+// terms, times 1.25. Returns false (the count keeps the band tables for r and
+// mu) for bins that start above 0 or when beta would leave no room.
+static bool r_space_band(const cute_binning* b, const ErrModel& em, Plan& pl) {
+    CountArgs& a = pl.a;
+    const int n1 = b->n1;
+    if (pl.T1[0] != 0.0) return false;
+    const double u = kU32, A = (double)a.e1a, S1 = (double)a.s1;
+    double beta = 0.0;
+    for (int k = 1; k <= n1; k++) {
+        const double ek = std::sqrt(pl.T1[k]) * (1.0 + 4.0 * kU64);
+        const double m = 1.5 * d2_bound(ek * (1.0 + 1e-6) + 2.0 * em.ec, em.ec, em.ec64) +
+                         4.0 * kU64 * pl.T1[k];
+        const double rr = ek * 1.01 + 2.0 * em.ec;
+        const double err = A * rr * kRsqRel + u * A * (rr + std::fabs(S1)) * 1.01 + 0x1p-24;
+        const double dev = std::fabs(A * (ek + S1) - ((double)k - 0.5)) + A * ek * 8.0 * kU64 + 1e-12;
+        beta = std::max(beta, err + dev + A * m / (1.5 * ek));
+    }
+    beta *= 1.25;
+    if (!(beta < 0.25)) return false;
+    a.rB0 = dn32(0.5 - beta);
+    return true;
+}
+
 // FP32 rounding bands of the decision thresholds under the error model em.
 void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
     CountArgs& a = pl.a;
@@ -556,7 +596,10 @@ void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
             a.dA0p = up32(A0 - A1 * (double)a.s1 + 2.0 * kU32 * A1 * std::fabs((double)a.s1));
         else
             a.dA0p = up32(A0);
-        if (!a.d2_generic && !a.d2_partial) mu_space_band(b, em, pl);
+        // the decisions in bin units (E_MUF): mu always, r with linear bins
+        a.rB0 = -1.0f;
+        if (!a.d2_generic && !a.d2_partial && (pl.est != E_LIN || r_space_band(b, em, pl)))
+            mu_space_band(b, em, pl);
     } else if (pl.mode == M_RMU_MID || pl.mode == M_SIGMAPI) {
         midpoint_bands(b, em, pl);
     }

@@ -453,6 +453,26 @@ cute_status cute_xi_multipoles(const double* xi_rmu, const cute_binning* bins, i
 cute_status cute_fp32_decision_tables(const cute_binning* bins, const double* err,
                                       float* band1, float* band2, float* consts);
 
+/* Host-only diagnostic: the FP32 decision constants of an RMU count with the
+ * z line of sight (r and mu = |dz| / r of Sec. 2.1), built exactly as a
+ * count builds them for a given FP32 error model. No device work; it exists
+ * so that the rounding analysis can be checked against exact arithmetic
+ * without a GPU.
+ * err[2]: bounds per component on |FP32 s - s| and on |FP64 s - s|
+ * (s = p - q).
+ * consts: 9 floats: e1a, s1, e2a, s2 (the FP32 maps x1 = fl(r + s1) e1a and
+ * x2 = fl(mu + s2) e2a, bin k along a dimension being x in [k - 1/2,
+ * k + 1/2)), rB0, muB1, muB0 (a pair is certified inside its r bin k when
+ * |x1 - k| <= rB0, inside its mu bin j when |x2 - j| <= muB1 / r + muB0),
+ * out_hi (pairs with FP32 |s|^2 >= out_hi are out of range), and the path:
+ * 2 when both r and mu are decided so (linear r bins from 0, mu bins
+ * linear over [0, 1]), 3 when only mu is (logarithmic r bins), 0 or 1 when
+ * the count uses the band tables instead (then rB0, muB1, muB0 are not
+ * used).
+ * Errors: CUTE_E_INVALID_ARG (bad binning, NULL, negative or non-finite
+ * error bounds), CUTE_E_UNSUPPORTED (other binnings or lines of sight). */
+cute_status cute_fp32_zlos_constants(const cute_binning* bins, const double* err, float* consts);
+
 const char* cute_status_string(cute_status s);
 
 /* Message of the last failed call on this thread ("" if none). */

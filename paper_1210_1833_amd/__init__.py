@@ -33,6 +33,7 @@ EXPORTED = ["cute_build_grid", "cute_free_grid", "cute_get_grid_info", "cute_cou
             "cute_count_jackknife_cross",
             "cute_build_pixel_map", "cute_pixel_map_read", "cute_count_radial",
             "cute_xi_estimate", "cute_xi_multipoles", "cute_fp32_decision_tables",
+            "cute_fp32_zlos_constants",
             "cute_status_string", "cute_last_error"]
 
 
@@ -152,6 +153,8 @@ def load():
                                        ctypes.POINTER(ctypes.c_int32), dp]
     lib.cute_fp32_decision_tables.restype = ctypes.c_int
     lib.cute_fp32_decision_tables.argtypes = [ctypes.POINTER(CBinning), dp, vp, vp, vp]
+    lib.cute_fp32_zlos_constants.restype = ctypes.c_int
+    lib.cute_fp32_zlos_constants.argtypes = [ctypes.POINTER(CBinning), dp, vp]
     lib.cute_status_string.restype = ctypes.c_char_p
     lib.cute_status_string.argtypes = [ctypes.c_int]
     lib.cute_last_error.restype = ctypes.c_char_p
@@ -689,3 +692,21 @@ def fp32_decision_tables(binning: Binning, ec: float, ec64: float, el: float, el
                                          err.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          b1.ctypes.data, b2.ctypes.data, c.ctypes.data))
     return b1, b2[:n2], dict(zip(DECISION_CONSTS, c.tolist()))
+
+
+ZLOS_CONSTS = ("e1a", "s1", "e2a", "s2", "rB0", "muB1", "muB0", "out_hi", "path")
+
+
+def fp32_zlos_constants(binning: Binning, ec: float, ec64: float):
+    """cute_fp32_zlos_constants (host only): the FP32 decision constants of
+    an RMU count with the z line of sight for a given error model, as a dict
+    (float32 values; "path" 2: r and mu in bin units, 3: mu only, 0 or 1:
+    band tables)."""
+    lib = load()
+    cb = binning.c()
+    err = np.array([ec, ec64], dtype=np.float64)
+    c = np.zeros(len(ZLOS_CONSTS), dtype=np.float32)
+    _check(lib.cute_fp32_zlos_constants(ctypes.byref(cb),
+                                        err.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        c.ctypes.data))
+    return dict(zip(ZLOS_CONSTS, c.tolist()))

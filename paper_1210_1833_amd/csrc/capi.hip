@@ -643,6 +643,28 @@ extern "C" cute_status cute_fp32_decision_tables(const cute_binning* bins, const
     return CUTE_OK;
 }
 
+extern "C" cute_status cute_fp32_zlos_constants(const cute_binning* bins, const double* err,
+                                                float* consts) {
+    cute_status s;
+    if ((s = validate_binning(bins)) != CUTE_OK) return s;
+    if (bins->kind != CUTE_BIN_RMU || bins->los != CUTE_LOS_Z)
+        return fail(CUTE_E_UNSUPPORTED, "z line-of-sight constants are reported for RMU with CUTE_LOS_Z only");
+    if (!err || !consts) return fail(CUTE_E_INVALID_ARG, "NULL argument");
+    for (int k = 0; k < 2; k++)
+        if (!std::isfinite(err[k]) || err[k] < 0.0)
+            return fail(CUTE_E_INVALID_ARG, "error bounds must be finite and >= 0");
+    Plan pl;
+    plan_binning(bins, pl);
+    ErrModel em;
+    em.ec = err[0];
+    em.ec64 = err[1];
+    plan_bands(bins, em, pl);
+    const CountArgs& a = pl.a;
+    const float c[9] = {a.e1a, a.s1, a.e2a, a.s2, a.rB0, a.muB1, a.muB0, a.out_hi, (float)pl.est};
+    for (int k = 0; k < 9; k++) consts[k] = c[k];
+    return CUTE_OK;
+}
+
 extern "C" cute_status cute_xi_estimate(cute_estimator e, const uint64_t* dd, const uint64_t* dr,
                                         const uint64_t* rr, int64_t nd, int64_t nr,
                                         const cute_binning* bins, double box_size, double* xi) {

@@ -611,8 +611,13 @@ def mode_leg(cute, torch, dev, kind, reps=2):
             "fp32_only_hist_l1": l1, "flips": int(st["flips"]),
             "gpair_evals_per_s": round(st["pair_evals"] / (ms * 1e-3) / 1e9, 1),
             "speedup_fp32edge_vs_fp64": round(res["fp64"][1]["ms_count"] / ms, 3),
-            "valu_frac": round(st["pair_evals"] * i_alg / (ms * 1e-3) / PEAK_LANE_OPS, 4),
-            "i_alg": i_alg, "host_s": round(t_gen, 1)}
+            "lane_op_frac_at_i_alg": round(st["pair_evals"] * i_alg / (ms * 1e-3) / PEAK_LANE_OPS, 4),
+            "i_alg": i_alg,
+            "lane_op_note": "i_alg lane-ops counted for every candidate pair, also those of steps "
+                            "dropped after the top-edge vote (a few operations each), so the "
+                            "fraction can pass 1; the VALU instructions actually issued per pair "
+                            "and the issue share are in the rocprofv3 counter summaries",
+            "host_s": round(t_gen, 1)}
 
 
 def fp32_only_leg(cute, xyz, bn, counts, c_exact, st_edge, reps=3):

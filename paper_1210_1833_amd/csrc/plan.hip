@@ -466,8 +466,9 @@ static void midpoint_bands(const cute_binning* b, const ErrModel& em, Plan& pl) 
 
 // The mu decision of the z line of sight in mu space (linear mu edges
 // covering [0, 1]). The kernel forms ts2 = fl(|dz32| rsq(v) + s2) and
-// tq = fl(ts2 a + 1/2), the pair's position in bin units (edge j at j), and
-// takes bin floor(tq) when frac(tq) is at least beta from 0 and from 1.
+// x = ts2 a, the pair's position in bin units (bin j is x in [j - 1/2,
+// j + 1/2)), and takes its estimated bin j (clamped to the bins) when the
+// offset fl(x - j) is at most 1/2 - beta in size.
 // With mu = |dz| / r exact, |dz32 - dz| <= ec, |v - r^2| <= D(r) (the d2
 // bound) and rsq within kRsqRel:
 //   |mu32 - mu| <= (1 + sqrt 3) ec / r + 1.5 ec^2 / r^2 + 1.51 u + kRsqRel
@@ -478,9 +479,10 @@ static void midpoint_bands(const cute_binning* b, const ErrModel& em, Plan& pl) 
 //          + dev + a E64 + 2 u,
 // with s2* the exact shift, dev the largest distance of the caller's edges
 // (in bin units) from the integers, E64 = 8 u64 the canonical FP64 mu
-// decision's own error, and 2 u for fl(frac - 1/2) and the FP32 fma of the
-// half-width. Kept as 1/2 - beta = muB1 rsq(v) + muB0, times a safety
-// factor 1.5 on beta.
+// decision's own error, and 2 u for the rounding of the offset and the FP32
+// fma of the half-width (the term u (a + |b| + 1) is a margin beyond these
+// roundings). Kept as 1/2 - beta =
+// muB1 rsq(v) + muB0, times a safety factor 1.5 on beta.
 static void mu_space_band(const cute_binning* b, const ErrModel& em, Plan& pl) {
     CountArgs& a = pl.a;
     const int n2 = b->n2;

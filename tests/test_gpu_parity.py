@@ -342,6 +342,21 @@ def test_far_from_the_origin_and_offset_grids(offset):
                los=cute.LOS_MIDPOINT)
 
 
+def test_rmu_fine_bins_far_apart_points():
+    """r bins 5e-4 wide (r < 0.01) over a catalog 1000 across: the FP32
+    coordinate error is a large part of a bin, so the count keeps the band
+    tables for r and mu (cute_fp32_zlos_constants reports which). Close
+    companions of spread-out anchors give pairs in every bin; FP64 and
+    FP32_EDGE equal the oracle."""
+    rng = np.random.default_rng(777)
+    anchors = rng.uniform(0.0, 1000.0, (1500, 3))
+    d = rng.normal(size=(1500, 3))
+    d *= (rng.uniform(0.0, 0.011, 1500) / np.linalg.norm(d, axis=1))[:, None]
+    pts = np.concatenate([anchors, anchors + d])
+    check_case("rmu-fine-bins", pts, None, cute.BIN_RMU, np.linspace(0.0, 0.01, 21),
+               np.linspace(0, 1, 11))
+
+
 def test_periodic_rmax_close_to_half_box():
     """r_max = 0.49 L in a periodic box: every pair is still counted once
     (minimum image), against the oracle. Closer to L/2 a tile and its reach

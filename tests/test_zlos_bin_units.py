@@ -184,6 +184,11 @@ def test_zlos_constants_paths():
     assert cute.fp32_zlos_constants(rmin, 1e-4, 1e-12)["path"] in (0.0, 1.0)
     part = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, np.arange(26) / 50.0, los=cute.LOS_Z)
     assert cute.fp32_zlos_constants(part, 1e-4, 1e-12)["path"] in (0.0, 1.0)
+    # r bins so fine against the coordinate error that the r band would be a
+    # large part of a bin: the band tables again
+    fine = cute.Binning(cute.BIN_RMU, np.linspace(0.0, 0.01, 21), me, los=cute.LOS_Z)
+    assert cute.fp32_zlos_constants(fine, 6e-5, 1e-12)["path"] in (0.0, 1.0)
+    assert cute.fp32_zlos_constants(fine, 1e-9, 1e-15)["path"] == 2.0
     mid = cute.Binning(cute.BIN_RMU, np.arange(41) * 5.0, me, los=cute.LOS_MIDPOINT)
     with pytest.raises(cute.CuteError):
         cute.fp32_zlos_constants(mid, 1e-4, 1e-12)

@@ -276,6 +276,13 @@ __device__ __forceinline__ float est_offset(float ts, float a, const Tab32& T, u
     return fmaf(ts, a, __uint_as_float(T.vbias) - __uint_as_float(kbits));
 }
 
+// v inside the band [lo, hi'] of its bin (hi' the largest float below the
+// upper threshold; an empty band is (inf, inf)): one med3 and one compare,
+// whose result is the mask itself
+__device__ __forceinline__ bool in_band(float v, float2 b) {
+    return __builtin_amdgcn_fmed3f(v, b.x, b.y) == v;
+}
+
 __device__ __forceinline__ float2 band_at(uint32_t tb, uint32_t kb) {
     const f2v b = *(lds_f2p)(uintptr_t)((kb << 3) + tb);
     return make_float2(b.x, b.y);
@@ -307,7 +314,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         }
         c.kb = est_bits(ts, P.e1a, T, P.top1);
         float2 b = band_at(T.tb1, c.kb);
-        c.in = (v >= b.x) & (v < b.y);
+        c.in = in_band(v, b);
         c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);
         if (WANT_TENT) *tent = (v >= P.bot32 & v < P.top32) ? c.kb - kBias : kNoBin;
         return c;
@@ -330,7 +337,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
             rin = fabsf(est_offset(ts, P.e1a, T, c.kb)) <= P.rB0;
         } else {
             float2 b = band_at(T.tb1, c.kb);
-            rin = (v >= b.x) & (v < b.y);
+            rin = in_band(v, b);
         }
         bool min_;
         if (est_muf(EST) && !WANT_TENT) {
@@ -381,7 +388,7 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
                                 fmaf(P.dC2, v, P.dC0)));
         float flo = fmaf(m.x, w, sl2);
         float fhi = fmaf(m.y, w, sl2);
-        bool rin = (v >= b.x) & (v < b.y);
+        bool rin = in_band(v, b);
         bool min_ = (flo >= delta) & (fhi <= -delta);
         c.in = rin & min_ & (ll >= P.llg);
         c.out = LO ? (v >= P.out_hi) | (v < P.out_lo) : (v >= P.out_hi);

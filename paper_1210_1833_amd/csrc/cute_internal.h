@@ -108,7 +108,8 @@ struct CountArgs {
     float sp_wstop, sp_wptop, sp_wsbot, sp_wpbot;
     int sp_low;
     // tables (global; staged into LDS)
-    const float2* band1;            // n1 entries: (lo_k, hi_{k+1}) FP32 band thresholds of dim 1
+    const float2* band1;            // n1 entries: (lo_k, below(hi_{k+1})) FP32 band thresholds of dim 1
+                                    // (SIGMAPI: the w of the lower and upper edges)
     const float2* band2;            // n2 entries: (-T2f[k] or +BIG, -T2f[k+1] or -BIG)
     const double* T1;               // n1+1 canonical FP64 thresholds of dim 1
     const double* T2;               // n2+1 canonical FP64 thresholds of dim 2

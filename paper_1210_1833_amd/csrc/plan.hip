@@ -573,8 +573,15 @@ void plan_bands(const cute_binning* b, const ErrModel& em, Plan& pl) {
             const double h = pl.T1[k] - m;
             hi_e[k] = h > 0.0 ? dn32(h) : -1.0f;
         }
+        // bin k certifies lo_e[k] <= v < hi_e[k+1]; the kernel tests
+        // med3(v, lo, hi') == v with hi' the largest float below hi_e[k+1],
+        // and a band that holds no float is (inf, inf), which no v equals
         pl.band1.resize(n1);
-        for (int k = 0; k < n1; k++) pl.band1[k] = make_float2(lo_e[k], hi_e[k + 1]);
+        for (int k = 0; k < n1; k++) {
+            const float lo = lo_e[k], hi = hi_e[k + 1];
+            pl.band1[k] = lo < hi ? make_float2(lo, std::nextafter(hi, -INFINITY))
+                                  : make_float2(INFINITY, INFINITY);
+        }
         a.out_hi = lo_e[n1];
         a.out_lo = hi_e[0];
         a.skip32 = a.out_hi;

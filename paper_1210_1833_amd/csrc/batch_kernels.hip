@@ -9,6 +9,8 @@
 // ordered by the estimated cost of their item, largest first, so that the
 // small items fill the tail of the launch. Point masks (bits in sorted order)
 // leave excluded home points and neighbour lanes idle.
+#include <type_traits>
+
 #include "count_device.h"
 
 namespace cute {
@@ -18,15 +20,16 @@ namespace {
 typedef const __attribute__((address_space(4))) CountArgs* cargp;
 
 // Sum the workgroup's histogram copies into counts (one atomic per non-empty
-// bin) and clear them.
-__device__ void flush_hist(unsigned long long* hist0, int nbins, int copies,
-                           unsigned long long* counts) {
+// bin) and clear them (counters of 4 bytes when H32, else 8).
+template <bool H32>
+__device__ void flush_hist(unsigned char* hist0, int nbins, int copies, unsigned long long* counts) {
+    typedef typename std::conditional<H32, uint32_t, unsigned long long>::type word;
     for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
         uint64_t s = 0;
-        unsigned long long* hh = hist0 + (size_t)b * copies;
+        word* hh = reinterpret_cast<word*>(hist0) + (size_t)b * copies;
         for (int c = 0; c < copies; c++) {
             s += hh[c];
-            hh[c] = 0ull;
+            hh[c] = 0;
         }
         if (s) atomicAdd(&counts[b], (unsigned long long)s);
     }
@@ -44,22 +47,29 @@ __global__ __launch_bounds__(256, 4) void k_count_batch(BatchArgs BA) {
     double* T2 = T1 + (n1 + 1);
     float2* B1 = reinterpret_cast<float2*>(T2 + (n2p + 1));
     float2* B2 = B1 + n1;
-    unsigned long long* hist0 = reinterpret_cast<unsigned long long*>(B2 + (n2p > 0 ? n2p : 1));
-    uint32_t* q0 = reinterpret_cast<uint32_t*>(hist0 + BA.hist_words);
+    constexpr bool H32 = kH32<MODE>;
+    // the histogram: hist_words counters of 4 (kH32) or 8 bytes, padded to 8
+    unsigned char* hist0 = reinterpret_cast<unsigned char*>(B2 + (n2p > 0 ? n2p : 1));
+    const size_t hbytes = ((size_t)BA.hist_words * (H32 ? 4 : 8) + 7) & ~(size_t)7;
+    uint32_t* q0 = reinterpret_cast<uint32_t*>(hist0 + hbytes);
     unsigned long long* rs0 = reinterpret_cast<unsigned long long*>(q0 + (size_t)nwaves * 3 * kQCap);
     uint32_t* sp0 = reinterpret_cast<uint32_t*>(rs0 + 2 * nwaves);
     uint32_t* ctl = sp0 + (size_t)nwaves * 3 * kSpanCap;  // chunk id, item, next tile, end tile
+    uint32_t* budget = ctl + 4;                           // 32-bit histograms only
     for (int i = threadIdx.x; i <= n1; i += blockDim.x) T1[i] = BA.T1[i];
     for (int i = threadIdx.x; i <= n2p; i += blockDim.x) T2[i] = n2p ? BA.T2[i] : 0.0;
     if (PREC != P_FP64) {
         for (int i = threadIdx.x; i < n1; i += blockDim.x) B1[i] = BA.band1[i];
         for (int i = threadIdx.x; i < n2p; i += blockDim.x) B2[i] = BA.band2[i];
     }
-    for (int i = threadIdx.x; i < BA.hist_words; i += blockDim.x) hist0[i] = 0ull;
+    for (size_t i = threadIdx.x; i < hbytes / 4; i += blockDim.x) reinterpret_cast<uint32_t*>(hist0)[i] = 0u;
     for (int i = threadIdx.x; i < 2 * nwaves; i += blockDim.x) rs0[i] = 0ull;
+    if (H32 && threadIdx.x == 0) *budget = 0u;
 
     WaveState W;
     W.hist = hist0;
+    W.budget = budget;
+    W.pend = 0;
     W.qi = q0 + (size_t)wave * 3 * kQCap;
     W.qj = W.qi + kQCap;
     W.qc = W.qj + kQCap;
@@ -93,7 +103,8 @@ __global__ __launch_bounds__(256, 4) void k_count_batch(BatchArgs BA) {
         if (item != cur) {
             if (cur != 0xffffffffu) {
                 const CountArgs& Pc = *(const CountArgs*)(cargp)(const void*)(BA.items + cur);
-                flush_hist(hist0, BA.nbins, BA.copies, Pc.counts);
+                flush_hist<H32>(hist0, BA.nbins, BA.copies, Pc.counts);
+                if (H32 && threadIdx.x == 0) *budget = 0u;
                 __syncthreads();
             }
             cur = item;
@@ -128,7 +139,7 @@ __global__ __launch_bounds__(256, 4) void k_count_batch(BatchArgs BA) {
     }
     if (cur != 0xffffffffu) {
         const CountArgs& Pc = *(const CountArgs*)(cargp)(const void*)(BA.items + cur);
-        flush_hist(hist0, BA.nbins, BA.copies, Pc.counts);
+        flush_hist<H32>(hist0, BA.nbins, BA.copies, Pc.counts);
     }
 }
 

@@ -458,29 +458,76 @@ __device__ __forceinline__ double shift64(uint32_t code, int axis, double L) {
 // in LDS; the rare paths below are real (non-inlined) calls that take the
 // queue length by value and return it, so the hot loop keeps few registers.
 struct WaveState {
-    unsigned long long* hist;  // the workgroup's shared 64-bit histogram (hist_words)
+    unsigned char* hist; // the workgroup's shared histogram (hist_words counters, kH32)
     uint32_t* qi;        // re-test queue: home index
     uint32_t* qj;        // re-test queue: neighbour index
     uint32_t* qc;        // re-test queue: neighbour image code
     unsigned long long* rstat;  // [0] retests, [1] flips (LDS)
     uint32_t tail;       // queued entries (wave-uniform)
     uint64_t evals, tiles;
+    // 32-bit histograms: the workgroup's budget of pair evaluations since the
+    // histogram was last moved to the global counts (LDS), and this wave's
+    // evaluations not reported to it yet
+    uint32_t* budget;
+    uint32_t pend;
 };
 
-// The workgroup's histogram: 64-bit LDS counters (no overflow, so no
-// flushing before the end of the kernel), several interleaved copies so that
-// lanes hitting the same bin use different banks. copies is a power of two:
-// word = (bin << log2(copies)) | (lane & (copies - 1)).
-__device__ __forceinline__ void hist_add(unsigned long long* hist, uint32_t bin, int copies,
-                                         int lane, uint64_t w = 1u) {
+// The workgroup's histogram: several interleaved copies so that lanes
+// hitting the same bin use different banks, copies a power of two: counter =
+// (bin << log2(copies)) | (lane & (copies - 1)). 64-bit counters never wrap;
+// 32-bit ones (kH32) are moved to the global counts in time (h32_flush).
+template <bool H32>
+__device__ __forceinline__ void hist_add(unsigned char* hist, uint32_t bin, int copies, int lane,
+                                         uint64_t w = 1u) {
     const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
-    atomicAdd(&hist[(bin << lc) | (uint32_t)(lane & (copies - 1))], (unsigned long long)w);
+    const uint32_t k = (bin << lc) | (uint32_t)(lane & (copies - 1));
+    if constexpr (H32)
+        atomicAdd(reinterpret_cast<uint32_t*>(hist) + k, (uint32_t)w);
+    else
+        atomicAdd(reinterpret_cast<unsigned long long*>(hist) + k, (unsigned long long)w);
 }
 
 // One increment at an LDS byte address (the lane's copy already folded in).
+template <bool H32>
 __device__ __forceinline__ void lds_add(uint32_t byte_addr, uint64_t w) {
-    __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned long long*)(uintptr_t)byte_addr,
-                           (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if constexpr (H32)
+        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(uintptr_t)byte_addr,
+                               (uint32_t)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned long long*)(uintptr_t)byte_addr,
+                               (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Move a 32-bit histogram to the global counts (one wave): every counter is
+// swapped with zero, so increments of the other waves land either in the
+// value moved or in the emptied counter, and none is lost.
+__device__ __attribute__((noinline)) void h32_flush(uint32_t* hist, int words, int copies,
+                                                    unsigned long long* counts, int lane) {
+    const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
+    for (int w = lane; w < words; w += 64) {
+        const uint32_t v = atomicExch(&hist[w], 0u);
+        if (v) atomicAdd(&counts[(uint32_t)w >> lc], (unsigned long long)v);
+    }
+}
+
+// Account the pair evaluations of a chunk to the workgroup's budget of a
+// 32-bit histogram (every pair adds at most wmax to one counter). A wave
+// reports its evaluations every h32_report of them; the wave that finds the
+// budget at h32_flush or more resets it and moves the histogram. A counter
+// then holds at most h32_flush plus what the waves have not reported or were
+// adding during the move (a few h32_report), far below 2^32.
+__device__ __forceinline__ void h32_account(const CountArgs& P, WaveState& W, int lane,
+                                            uint32_t evals) {
+    W.pend += evals;
+    if (W.pend < P.h32_report) return;
+    uint32_t old = 0;
+    if (lane == 0) old = atomicAdd(W.budget, W.pend);
+    old = uni(old);
+    const uint32_t now = old + W.pend;
+    W.pend = 0;
+    if (now < P.h32_flush) return;
+    if (lane == 0) atomicExch(W.budget, 0u);
+    h32_flush(reinterpret_cast<uint32_t*>(W.hist), P.hist_words, P.copies, P.counts, lane);
 }
 
 // Weight of a pair in a region pass: wsame if the neighbour lies in the home
@@ -502,7 +549,7 @@ __device__ __forceinline__ uint64_t pair_weight2(const CountArgs& P, uint32_t i,
 // Returns the new queue length.
 template <int MODE, int EST>
 __device__ __attribute__((noinline)) uint32_t drain_queue(
-    const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
+    const CountArgs* __restrict__ Pg, unsigned char* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
     unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
     const double* T2, int lane, uint32_t tail, bool all) {
     const CountArgs& P = *Pg;
@@ -516,7 +563,7 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
             const P64 p = P.A.p64[i];
             const P64 q = P.B.p64[j];
             k = classify_pair64<MODE, EST>(P, T1, T2, p, q);
-            if (k != kNoBin) hist_add(hist, k, P.copies, lane, pair_weight2(P, i, j));
+            if (k != kNoBin) hist_add<kH32<MODE>>(hist, k, P.copies, lane, pair_weight2(P, i, j));
             // the FP32-only decision of the same pair, as the main loop made it
             const float4 a = P.A.p32[i];
             const float4 b = P.B.p32[j];
@@ -551,7 +598,7 @@ __device__ __attribute__((noinline)) uint32_t drain_queue(
 // neighbour). Drains whenever 64 or more pairs are waiting.
 template <int MODE, int EST>
 __device__ __attribute__((noinline)) uint32_t enqueue_chunk(
-    const CountArgs* __restrict__ Pg, unsigned long long* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
+    const CountArgs* __restrict__ Pg, unsigned char* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,
     unsigned long long* rstat, const float2* B1, const float2* B2, const double* T1,
     const double* T2, int lane, uint32_t tail, uint32_t ts, uint32_t lj, uint32_t lcode,
     uint64_t ambh, uint64_t hsum) {
@@ -688,7 +735,7 @@ __device__ __forceinline__ void step32(const CountArgs& P, WaveState& W, const T
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) lds_add(off[u], WT ? (uint64_t)lw * hw[u] : (uint64_t)lw);
+        if (cnt[u]) lds_add<kH32<MODE>>(off[u], WT ? (uint64_t)lw * hw[u] : (uint64_t)lw);
     if (PREC == P_FP32E && any_amb) {
         // remember the pair for the end of the chunk: bit (home - ts) of this
         // lane's mask, and the home offset in the wave's mask
@@ -800,7 +847,7 @@ __device__ __forceinline__ void step64(const CountArgs& P, WaveState& W, const d
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++)
-        if (cnt[u]) hist_add(W.hist, bin[u], P.copies, lane, WT ? (uint64_t)lw * hw[u] : (uint64_t)lw);
+        if (cnt[u]) hist_add<kH32<MODE>>(W.hist, bin[u], P.copies, lane, WT ? (uint64_t)lw * hw[u] : (uint64_t)lw);
 }
 
 // The chunk being assembled from neighbour spans (per-lane fields in VGPRs,
@@ -819,6 +866,11 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
                           const double* T1, const double* T2, int lane, Chunk& C, uint32_t ts,
                           uint32_t te) {
     constexpr uint32_t U = 4;
+    if constexpr (kH32<MODE>) {
+        // every pair of the chunk adds at most the largest region weight
+        const uint32_t wmax = P.regs == nullptr ? 1u : (P.wsame > P.wdiff ? P.wsame : P.wdiff);
+        h32_account(P, W, lane, C.filled * (te - ts) * wmax);
+    }
     bool lvalid = (uint32_t)lane < C.filled;
     // a neighbour excluded by the point mask leaves its lane idle
     if (PM && P.mbB != nullptr && lvalid) lvalid = ((P.mbB[C.lj >> 5] >> (C.lj & 31u)) & 1u) == 0u;
@@ -854,7 +906,8 @@ __device__ void run_chunk(const CountArgs& P, WaveState& W, const float2* B1, co
     } else {
         // wave-uniform constants in VGPRs, and this lane's histogram copy
         const Tab32 tab = make_tab32<EST>(P, B1, B2);
-        const uint32_t lb = lds_addr(W.hist) + ((uint32_t)lane & (uint32_t)(P.copies - 1)) * 8u;
+        const uint32_t lb = lds_addr(W.hist) +
+                            ((uint32_t)lane & (uint32_t)(P.copies - 1)) * (kH32<MODE> ? 4u : 8u);
         // the neighbour in the home grid's FP32 frame: q - (cA - cB) for two
         // open grids, or its periodic image q + k L (only one of the two is
         // ever non-zero), and q + 2 cA for the midpoint line of sight

@@ -47,22 +47,29 @@ __global__ __launch_bounds__(256, (kWgPerCu<MODE, PREC>)) void k_count(CountArgs
     double* T2 = T1 + (n1 + 1);
     float2* B1 = reinterpret_cast<float2*>(T2 + (n2p + 1));
     float2* B2 = B1 + n1;
-    unsigned long long* hist0 = reinterpret_cast<unsigned long long*>(B2 + (n2p > 0 ? n2p : 1));
-    uint32_t* q0 = reinterpret_cast<uint32_t*>(hist0 + P.hist_words);
+    constexpr bool H32 = kH32<MODE>;
+    // the histogram: hist_words counters of 4 (kH32) or 8 bytes, padded to 8
+    unsigned char* hist0 = reinterpret_cast<unsigned char*>(B2 + (n2p > 0 ? n2p : 1));
+    const size_t hbytes = ((size_t)P.hist_words * (H32 ? 4 : 8) + 7) & ~(size_t)7;
+    uint32_t* q0 = reinterpret_cast<uint32_t*>(hist0 + hbytes);
     unsigned long long* rs0 = reinterpret_cast<unsigned long long*>(q0 + (size_t)nwaves * 3 * kQCap);
     uint32_t* sp0 = reinterpret_cast<uint32_t*>(rs0 + 2 * nwaves);
+    uint32_t* budget = sp0 + (size_t)nwaves * 3 * kSpanCap;  // 32-bit histograms only
     for (int i = threadIdx.x; i <= n1; i += blockDim.x) T1[i] = P.T1[i];
     for (int i = threadIdx.x; i <= n2p; i += blockDim.x) T2[i] = n2p ? P.T2[i] : 0.0;
     if (PREC != P_FP64) {
         for (int i = threadIdx.x; i < n1; i += blockDim.x) B1[i] = P.band1[i];
         for (int i = threadIdx.x; i < n2p; i += blockDim.x) B2[i] = P.band2[i];
     }
-    for (int i = threadIdx.x; i < P.hist_words; i += blockDim.x) hist0[i] = 0ull;
+    for (size_t i = threadIdx.x; i < hbytes / 4; i += blockDim.x) reinterpret_cast<uint32_t*>(hist0)[i] = 0u;
     for (int i = threadIdx.x; i < 2 * nwaves; i += blockDim.x) rs0[i] = 0ull;
+    if (H32 && threadIdx.x == 0) *budget = 0u;
     __syncthreads();
 
     WaveState W;
     W.hist = hist0;
+    W.budget = budget;
+    W.pend = 0;
     W.qi = q0 + (size_t)wave * 3 * kQCap;
     W.qj = W.qi + kQCap;
     W.qc = W.qj + kQCap;
@@ -102,8 +109,13 @@ __global__ __launch_bounds__(256, (kWgPerCu<MODE, PREC>)) void k_count(CountArgs
     // sum the copies, then one global atomic per non-empty bin
     for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) {
         uint64_t s = 0;
-        const unsigned long long* hh = hist0 + (size_t)b * P.copies;
-        for (int c = 0; c < P.copies; c++) s += hh[c];
+        if constexpr (H32) {
+            const uint32_t* hh = reinterpret_cast<const uint32_t*>(hist0) + (size_t)b * P.copies;
+            for (int c = 0; c < P.copies; c++) s += hh[c];
+        } else {
+            const unsigned long long* hh = reinterpret_cast<const unsigned long long*>(hist0) + (size_t)b * P.copies;
+            for (int c = 0; c < P.copies; c++) s += hh[c];
+        }
         if (s) atomicAdd(&P.counts[b], (unsigned long long)s);
     }
 }

@@ -36,6 +36,14 @@ constexpr bool est_muf(int e) { return (e & E_MUF) != 0; }
 // Precision path.
 enum Prec : int { P_FP64 = 0, P_FP32E = 1, P_FP32O = 2 };
 
+// LDS histogram counters: 32-bit for the midpoint kinds (their two-dimensional
+// histograms are large, and half the bytes keeps more workgroups on a CU),
+// 64-bit for the others. A 32-bit histogram is moved to the global counts
+// before any counter can wrap (see h32_flush).
+template <int MODE>
+constexpr bool kH32 = MODE == M_SIGMAPI || MODE == M_RMU_MID;
+constexpr bool h32_mode(int mode) { return mode == M_SIGMAPI || mode == M_RMU_MID; }
+
 // A home tile: a run of sorted points inside one row of cells.
 struct Tile {
     uint32_t start, end;  // sorted point range [start, end)
@@ -77,7 +85,11 @@ struct CountArgs {
     int n1, n2, nbins;
     float n1m1, n2m1;               // n1 - 1 and n2 - 1 as floats (estimate clamps)
     int copies;                     // LDS histogram copies per wave (power of two)
-    int hist_words;                 // nbins * copies
+    int hist_words;                 // nbins * copies (counters of 4 or 8 bytes, kH32)
+    // 32-bit histograms: a wave reports its pair evaluations to the
+    // workgroup's budget once it has h32_report of them, and the histogram is
+    // moved to counts once the budget reaches h32_flush (< 2^31)
+    uint32_t h32_report, h32_flush;
     // FP32 geometry constants
     float offx, offy, offz;         // FP32(cA - cB), added to home points (open boxes)
     float lcx, lcy, lcz;            // FP32(2 cB): l = home_eff + q + lc (midpoint LOS)
@@ -119,8 +131,8 @@ struct CountArgs {
     float s1, s2;
     uint32_t top1, top2;
     int n2p1;
-    // LDS histogram strides in bytes: dimension 1 (n2p1 << log2 copies << 3)
-    // and dimension 2 (8 << log2 copies)
+    // LDS histogram strides in bytes: dimension 1 (n2p1 << log2 copies times
+    // the counter size) and dimension 2 (copies times the counter size)
     int hs1, hs2;
     // constant term of the mu band of the z line of sight as the kernel uses
     // it (dA0 for log r bins, dA0 - dA1 s1 plus its rounding for linear ones)

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "cute_internal.h"
@@ -625,11 +626,17 @@ cute_status plan_lds(Plan& pl, size_t extra) {
     const size_t tables = 8 * (size_t)(n1 + 1) + 8 * (size_t)(n2 + 1) + 8 * (size_t)n1 +
                           8 * (size_t)std::max(n2, 1);
     const size_t per_wave = 12 * (size_t)kQCap + 16 + 12 * (size_t)kSpanCap;
-    const size_t fixed = tables + (size_t)kWgWaves * per_wave + extra;
+    // extra: the kernel's control words after the span buffers, plus the
+    // budget word of a 32-bit histogram; a 32-bit histogram's bytes are
+    // rounded up to 8
+    const bool h32 = h32_mode(pl.mode);
+    const size_t es = h32 ? 4 : 8;   // bytes per counter
+    const size_t fixed = tables + (size_t)kWgWaves * per_wave + extra + (h32 ? 16 : 0);
+    const size_t pad = h32 ? 4 : 0;
     int C = 0;
     for (size_t budget : {(size_t)40 * 1024, (size_t)80 * 1024, (size_t)160 * 1024}) {
-        if (fixed + 8 * (size_t)nbins > budget) continue;
-        size_t cmax = (budget - fixed) / (8 * (size_t)nbins);
+        if (fixed + pad + es * (size_t)nbins > budget) continue;
+        size_t cmax = (budget - fixed - pad) / (es * (size_t)nbins);
         C = 1;
         while (C * 2 <= (int)std::min<size_t>(cmax, 32)) C *= 2;
         break;
@@ -637,9 +644,20 @@ cute_status plan_lds(Plan& pl, size_t extra) {
     if (C == 0) return fail(CUTE_E_UNSUPPORTED, "histogram does not fit in LDS");
     a.copies = C;
     a.hist_words = nbins * C;
-    a.hs2 = 8 * C;
-    a.hs1 = a.n2p1 * 8 * C;
-    pl.lds = fixed + 8 * (size_t)a.hist_words;
+    a.hs2 = (int)es * C;
+    a.hs1 = a.n2p1 * (int)es * C;
+    a.h32_report = 1u << 20;
+    a.h32_flush = 1u << 30;
+    if (const char* t = std::getenv("CUTE_TEST_H32_FLUSH")) {
+        // test hook: a small flush threshold, so that the moves of a 32-bit
+        // histogram to the global counts happen many times in one count
+        const long v = std::strtol(t, nullptr, 10);
+        if (v > 0 && v < (1l << 30)) {
+            a.h32_flush = (uint32_t)v;
+            a.h32_report = std::max<uint32_t>(1u, (uint32_t)v / 4u);
+        }
+    }
+    pl.lds = fixed + ((es * (size_t)a.hist_words + 7) & ~(size_t)7);
     return CUTE_OK;
 }
 

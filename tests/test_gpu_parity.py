@@ -357,6 +357,47 @@ def test_rmu_fine_bins_far_apart_points():
                np.linspace(0, 1, 11))
 
 
+@pytest.mark.parametrize("flush", ["4096", "100000"])
+def test_midpoint_histograms_moved_during_the_count(flush):
+    """The midpoint kinds count in 32-bit LDS counters, moved to the global
+    counts before they can wrap. A small flush threshold (a test hook; the
+    count uses 2^30) makes the moves happen many times inside one count,
+    while the other waves keep adding: single counts, a batch and the
+    jackknife by regions still equal the oracle."""
+    import os
+    d, r = catalogs.clustered_box_1e6(n_centres=60, per_blob=40, n_rand=3000, box=200.0)
+    a = np.stack([d.x, d.y, d.z], axis=1) + 1500.0
+    b = np.stack([r.x, r.y, r.z], axis=1) + 1500.0
+    e = np.linspace(0.0, 20.0, 11)
+    os.environ["CUTE_TEST_H32_FLUSH"] = flush
+    try:
+        check_case("h32-sigmapi-auto-%s" % flush, a, None, cute.BIN_SIGMAPI, e, e,
+                   los=cute.LOS_MIDPOINT)
+        check_case("h32-sigmapi-cross-%s" % flush, a, b, cute.BIN_SIGMAPI, e, e,
+                   los=cute.LOS_MIDPOINT)
+        want = check_case("h32-rmumid-auto-%s" % flush, a, None, cute.BIN_RMU,
+                          np.linspace(0.0, 30.0, 7), np.linspace(0, 1, 6), los=cute.LOS_MIDPOINT)
+        bn = cute.Binning(cute.BIN_RMU, np.linspace(0.0, 30.0, 7), np.linspace(0, 1, 6),
+                          los=cute.LOS_MIDPOINT)
+        g = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=30.0)
+        items = [cute.BatchItem(g, None, bn), cute.BatchItem(g, None, bn)]
+        reg = (a[:, 0] > np.median(a[:, 0])).astype(np.int32) + 2 * (a[:, 1] > np.median(a[:, 1]))
+        ob = obin(cute.BIN_RMU, np.linspace(0.0, 30.0, 7), np.linspace(0, 1, 6), cute.LOS_MIDPOINT)
+        wt, wj = oracle.count_jackknife(a, reg, 4, ob)
+        for prec in EXACT:
+            say("case h32 batch prec %d flush %s" % (prec, flush))
+            got = cute.count_pairs_batched(items, prec)
+            for x in got:
+                np.testing.assert_array_equal(x.reshape(bn.shape), want)
+            say("case h32 jackknife prec %d flush %s" % (prec, flush))
+            tot, jack = cute.count_jackknife(g, reg, 4, bn, prec)
+            np.testing.assert_array_equal(tot.reshape(-1), wt.reshape(-1))
+            np.testing.assert_array_equal(jack.reshape(4, -1), wj.reshape(4, -1))
+        g.close()
+    finally:
+        del os.environ["CUTE_TEST_H32_FLUSH"]
+
+
 def test_periodic_rmax_close_to_half_box():
     """r_max = 0.49 L in a periodic box: every pair is still counted once
     (minimum image), against the oracle. Closer to L/2 a tile and its reach

@@ -36,7 +36,7 @@ __device__ void flush_hist(unsigned char* hist0, int nbins, int copies, unsigned
 }
 
 template <int MODE, int PREC, int EST>
-__global__ __launch_bounds__(256, 4) void k_count_batch(BatchArgs BA) {
+__global__ __launch_bounds__(256, (kWgPerCu<MODE, PREC>)) void k_count_batch(BatchArgs BA) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;

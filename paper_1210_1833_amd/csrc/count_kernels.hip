@@ -27,9 +27,6 @@ namespace cute {
 
 namespace {
 
-template <int MODE, int PREC>
-constexpr int kWgPerCu = (PREC == P_FP32E && (MODE == M_THETA || MODE == M_MONO)) ? 5 : 4;
-
 // Four 4-wave workgroups per CU: the register budget stays at 128 VGPRs.
 // The one-variable FP32_EDGE kernels (MONO, THETA) run five (96 VGPRs, the
 // few spills outside the pair steps), which hides more latency: the angular

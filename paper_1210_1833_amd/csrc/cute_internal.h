@@ -42,6 +42,11 @@ enum Prec : int { P_FP64 = 0, P_FP32E = 1, P_FP32O = 2 };
 // before any counter can wrap (see h32_flush).
 template <int MODE>
 constexpr bool kH32 = MODE == M_SIGMAPI || MODE == M_RMU_MID;
+
+// Workgroups per CU a count kernel is compiled for (its register budget):
+// five for the one-variable FP32_EDGE kernels, four for the others.
+template <int MODE, int PREC>
+constexpr int kWgPerCu = (PREC == P_FP32E && (MODE == M_THETA || MODE == M_MONO)) ? 5 : 4;
 constexpr bool h32_mode(int mode) { return mode == M_SIGMAPI || mode == M_RMU_MID; }
 
 // A home tile: a run of sorted points inside one row of cells.

@@ -29,6 +29,13 @@ def lds_bytes(n1, n2):
     return tables + 4 * PER_WAVE + 8 * n1 * max(n2, 1)
 
 
+def lds_bytes_h32(n1, n2):
+    """The same for the midpoint kinds: 32-bit counters (bytes rounded up to
+    8, with 4 more reserved) and 16 bytes for the histogram's budget word."""
+    tables = 8 * (n1 + 1) + 8 * (n2 + 1) + 8 * n1 + 8 * max(n2, 1)
+    return tables + 4 * PER_WAVE + 16 + 4 + 4 * n1 * max(n2, 1)
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     import torch
@@ -46,6 +53,30 @@ def say(*a):
 def test_lds_model_brackets_the_limits():
     assert lds_bytes(6183, 0) <= LDS_MAX < lds_bytes(6184, 0)
     assert lds_bytes(134, 134) <= LDS_MAX < lds_bytes(135, 135)
+    assert lds_bytes_h32(188, 188) <= LDS_MAX < lds_bytes_h32(189, 189)
+
+
+def test_largest_sigmapi_histogram():
+    """188 x 188 sigma-pi bins, the most 32-bit counters that fit (one
+    workgroup per CU), against the oracle; 189 x 189 is refused."""
+    rng = np.random.default_rng(205)
+    m = rng.uniform(900.0, 1100.0, (600, 3))
+    d = rng.normal(size=(600, 3)) * 8.0
+    a = np.concatenate([m, m + d])
+    e = np.linspace(0.0, 30.0, 189)
+    bn = cute.Binning(cute.BIN_SIGMAPI, e, e, los=cute.LOS_MIDPOINT)
+    ob = oracle.Binning(oracle.SIGMAPI, e, e, los=oracle.LOS_MID)
+    reach = float(np.hypot(30.0, 30.0)) * (1 + 1e-12)
+    g = cute.build_grid(a, cute.GEOM_BOX_OPEN, r_max=reach)
+    want = oracle.count_pairs(a, None, ob).reshape(bn.shape)
+    assert want.sum() > 0
+    for prec in EXACT:
+        say("SIGMAPI 188 x 188 bins, prec %d" % prec)
+        np.testing.assert_array_equal(cute.count_pairs(g, None, bn, prec), want)
+    e2 = np.linspace(0.0, 30.0, 190)
+    with pytest.raises(cute.CuteError) as ex:
+        cute.count_pairs(g, None, cute.Binning(cute.BIN_SIGMAPI, e2, e2, los=cute.LOS_MIDPOINT))
+    assert ex.value.status == cute.E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("n", [6183])

@@ -437,12 +437,14 @@ cute_status cute_xi_multipoles(const double* xi_rmu, const cute_binning* bins, i
  * be checked against exact arithmetic without a GPU.
  * err[4]: bounds per component on |FP32 s - s| (s = p - q), on |FP64 s - s|,
  * on |FP32 l - l| and on |FP64 l - l|.
- * band1: 2 * n1 floats, band2: 2 * n2 floats; per bin the threshold w of its
- * lower edge, then that of its upper edge: a pair is certified in the bin
- * along that dimension when F + w_lo ll >= t and F + w_hi ll <= -t, with
- * F = |s x l|^2 (sigma) or (s.l)^2 (pi), ll = |l|^2 and t = K1 |l| + K0
- * (SIGMAPI; for RMU the mu thresholds are the plain -mu_j^2 and the band is
- * delta below).
+ * band1: 2 * n1 floats, band2: 2 * n2 floats. SIGMAPI: per bin m and H, and
+ * a pair is certified in the bin along that dimension when
+ * |F + m ll| <= H ll - t, with F = |s x l|^2 (sigma) or (s.l)^2 (pi),
+ * ll = |l|^2 and t = K1 |l| + K0 (-m is the centre of the bin's certified
+ * interval of F/ll, H its half-width less the roundings of the two fmas; a
+ * bin with H < 0 is never certified). RMU: band1 holds per r bin the FP32
+ * bounds lo and hi' of |s|^2 (certified when lo <= |s|^2 <= hi'), band2 the
+ * plain -mu_j^2 of the mu thresholds, whose band is delta below.
  * consts: 17 floats: skip32 (pairs with FP32 |s|^2 >= skip32 are out of
  * range), llg (pairs with ll < llg are never decided in FP32), K1, K0,
  * w of sigma_max, of pi_max, of sigma_0, of pi_0, the low-side flag, then the

@@ -422,8 +422,10 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
         c.in = c.out = false;
         return c;
     }
-    // the per-edge parts of the bands are in the tables (F + w ll); the part
-    // from the direction error of l is t, in units of F
+    // the per-edge parts of the bands are in the tables; the part from the
+    // direction error of l is t, in units of F. A bin's entry is (m, H): the
+    // pair is inside it along that dimension when |F + m ll| <= H ll - t
+    // (F/ll within H - t/ll of the centre -m of the certified interval)
     float t = fmaf(P.spK1, ll * rl, P.spK0);
     float2 bs = band_at(T.tb1, c.kb);
     float2 bp = band_at(T.tb2, c.kmb);
@@ -431,8 +433,8 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
     // the direction error of l
     bool vin = v < P.skip32;
     bool lg = ll >= P.llg;
-    bool ins = (fmaf(bs.x, ll, c2) >= t) & (fmaf(bs.y, ll, c2) <= -t);
-    bool inp = (fmaf(bp.x, ll, sl2) >= t) & (fmaf(bp.y, ll, sl2) <= -t);
+    bool ins = fabsf(fmaf(bs.x, ll, c2)) <= fmaf(bs.y, ll, -t);
+    bool inp = fabsf(fmaf(bp.x, ll, sl2)) <= fmaf(bp.y, ll, -t);
     c.in = vin & lg & ins & inp;
     bool top = (fmaf(P.sp_wstop, ll, c2) >= t) | (fmaf(P.sp_wptop, ll, sl2) >= t);
     if (LO) top = top | (fmaf(P.sp_wsbot, ll, c2) <= -t) | (fmaf(P.sp_wpbot, ll, sl2) <= -t);

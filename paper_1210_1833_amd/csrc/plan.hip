@@ -412,17 +412,31 @@ static void midpoint_bands(const cute_binning* b, const ErrModel& em, Plan& pl) 
         std::vector<double> bs(n1 + 1), bp(n2 + 1);
         for (int k = 0; k <= n1; k++) bs[k] = band(pl.T1[k], 14.0);
         for (int k = 0; k <= n2; k++) bp[k] = band(pl.T2[k], 8.0);
-        // bin k: F + wlo ll >= t certifies x^2 >= T_k (a first edge at zero
-        // always holds: +BIG); F + whi ll <= -t certifies x^2 < T_{k+1}
-        // (an upper edge inside its own band, T <= b, is never certified: +BIG)
-        auto lo_w = [](double T, double bb) { return T == 0.0 ? kBig : dn32(-(T + bb)); };
-        auto hi_w = [](double T, double bb) { return T - bb <= 0.0 ? kBig : up32(-(T - bb)); };
+        // bin k certifies lo <= x^2 - t/ll and x^2 + t/ll <= hi, lo = T_k + b_k
+        // and hi = T_{k+1} - b_{k+1}, as |F + m ll| <= H ll - t with m the
+        // negated centre and H the half-width of [lo, hi]. A first edge at
+        // zero cannot be crossed: the interval is taken as [-hi, hi] (m = 0).
+        // With the FP32 m and the two roundings of the kernel's fmas (each at
+        // most u of its result), |fl(F + m ll)| <= fl(H ll - t) implies
+        // |F - c ll| <= (H (1 + 2.01 u) + |m + c|) ll - t, so H is stored as
+        // dn32((Hx - |m + c|) / (1 + 2.01 u)), Hx the exact half-width. A bin
+        // with no room (hi <= lo) gets H = -1: never certified.
+        auto mid_half = [&](double Tlo, double blo, double Thi, double bhi) {
+            const double hi = Thi - bhi;
+            const double lo = Tlo == 0.0 ? -hi : Tlo + blo;
+            if (!(hi > lo)) return make_float2(0.0f, -1.0f);
+            const double c = 0.5 * (lo + hi), hx = 0.5 * (hi - lo);
+            const float m = (float)(-c);
+            const double h = (hx - std::fabs((double)m + c)) / (1.0 + 2.01 * u);
+            return h > 0.0 ? make_float2(m, dn32(h)) : make_float2(0.0f, -1.0f);
+        };
         pl.band1.resize(n1);
         for (int k = 0; k < n1; k++)
-            pl.band1[k] = make_float2(lo_w(pl.T1[k], bs[k]), hi_w(pl.T1[k + 1], bs[k + 1]));
+            pl.band1[k] = mid_half(pl.T1[k], bs[k], pl.T1[k + 1], bs[k + 1]);
         pl.band2.resize(n2);
         for (int k = 0; k < n2; k++)
-            pl.band2[k] = make_float2(lo_w(pl.T2[k], bp[k]), hi_w(pl.T2[k + 1], bp[k + 1]));
+            pl.band2[k] = mid_half(pl.T2[k], bp[k], pl.T2[k + 1], bp[k + 1]);
+        auto hi_w = [](double T, double bb) { return T - bb <= 0.0 ? kBig : up32(-(T - bb)); };
         a.sp_wstop = dn32(-(pl.T1[n1] + bs[n1]));
         a.sp_wptop = dn32(-(pl.T2[n2] + bp[n2]));
         a.sp_wsbot = hi_w(pl.T1[0], bs[0]);

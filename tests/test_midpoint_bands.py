@@ -146,9 +146,11 @@ def sp_decisions(fr, b1, b2, k, p, q, pert):
     t = fma32(F32(k["K1"]), ll * rl, F32(k["K0"]))
     vin = v < F32(k["skip32"])
     lg = ll >= F32(k["llg"])
-    ins = [(fma32(F32(b1[i, 0]), ll, c2) >= t) and (fma32(F32(b1[i, 1]), ll, c2) <= -t)
+    # a bin's entry (m, H): inside when |F + m ll| <= H ll - t
+    nt = -t
+    ins = [abs(float(fma32(F32(b1[i, 0]), ll, c2))) <= float(fma32(F32(b1[i, 1]), ll, nt))
            for i in range(len(b1))]
-    inp = [(fma32(F32(b2[j, 0]), ll, sl2) >= t) and (fma32(F32(b2[j, 1]), ll, sl2) <= -t)
+    inp = [abs(float(fma32(F32(b2[j, 0]), ll, sl2))) <= float(fma32(F32(b2[j, 1]), ll, nt))
            for j in range(len(b2))]
     top = (fma32(F32(k["w_sigma_top"]), ll, c2) >= t) or (fma32(F32(k["w_pi_top"]), ll, sl2) >= t)
     if k["low"]:
@@ -202,10 +204,17 @@ def test_sigma_pi_bands_on_adversarial_light_cone_pairs(first):
                 ks = min(range(len(S2)), key=lambda a: abs(S2[a] - sig2))
                 kp = min(range(len(P2)), key=lambda a: abs(P2[a] - pi2))
                 ll = float(w["ll"])
-                bs_lo = -float(b1[min(ks, len(b1) - 1), 0]) - float(S2[ks]) if S2[ks] > 0 else 0.0
+                # the certified interval of bin j is about [-m - H, -m + H]; the
+                # band at an edge is its distance from the edge
+                def upper(b, j):
+                    return -float(b[j, 0]) + float(b[j, 1])
+
+                def lower(b, j):
+                    return -float(b[j, 0]) - float(b[j, 1])
+                bs_lo = lower(b1, min(ks, len(b1) - 1)) - float(S2[ks]) if S2[ks] > 0 else 0.0
                 # the bound: |FP32 sigma^2 - exact| <= band + t / ll
-                band_s = abs(-float(b1[ks - 1, 1]) - float(S2[ks])) if ks > 0 else bs_lo
-                band_p = abs(-float(b2[kp - 1, 1]) - float(P2[kp])) if kp > 0 else 0.0
+                band_s = abs(upper(b1, ks - 1) - float(S2[ks])) if ks > 0 else bs_lo
+                band_p = abs(upper(b2, kp - 1) - float(P2[kp])) if kp > 0 else 0.0
                 tl = float(w["t"]) / ll
                 sig2_32 = float(w["c2"]) / ll
                 pi2_32 = float(w["sl2"]) / ll

@@ -405,9 +405,13 @@ __device__ __forceinline__ C32 classify32(const CountArgs& P, const Tab32& T, fl
     float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
     float sl2 = sl * sl;
     float c2 = fmaf(v, ll, -sl2);
-    // sigma = sqrt(c2) / |l| and pi = |s.l| / |l| share one 1/|l|
+    // sigma = sqrt(c2) / |l| and pi = |s.l| / |l| share one 1/|l|. A c2
+    // rounded below zero (a pair all but along l) gives a NaN estimate,
+    // which the clamp puts in the last sigma bin, whose band test (on c2
+    // itself) then fails: the pair is re-tested. The FP32-only decision
+    // takes sigma = 0 instead.
     float rl = __builtin_amdgcn_rsqf(ll);
-    float sg = __builtin_amdgcn_sqrtf(fmaxf(c2, 0.0f)) * rl;
+    float sg = __builtin_amdgcn_sqrtf(WANT_TENT ? fmaxf(c2, 0.0f) : c2) * rl;
     float pp = fabsf(sl) * rl;
     c.kb = est_bits(sg + P.s1, P.e1a, T, P.top1);
     c.kmb = est_bits(pp + P.s2, P.e2a, T, P.top2);

@@ -28,9 +28,9 @@ namespace cute {
 namespace {
 
 // Four 4-wave workgroups per CU: the register budget stays at 128 VGPRs.
-// The one-variable FP32_EDGE kernels (MONO, THETA) run five (96 VGPRs, the
-// few spills outside the pair steps), which hides more latency: the angular
-// count takes 10 % less time; the r-mu and sigma-pi ones gain nothing.
+// The one-variable FP32_EDGE kernels (MONO, THETA) run five (96 VGPRs),
+// which hides more latency: the angular count takes 10 % less time; the r-mu
+// and sigma-pi ones gain nothing.
 // WT: pixel maps, each pair weighted by the product of the point weights.
 template <int MODE, int PREC, int EST, bool WT>
 __global__ __launch_bounds__(256, (kWgPerCu<MODE, PREC>)) void k_count(CountArgs P) {

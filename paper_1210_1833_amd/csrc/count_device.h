@@ -461,8 +461,7 @@ __device__ __forceinline__ double shift64(uint32_t code, int axis, double L) {
 }
 
 // Per-wave state. The queue, the histogram and the re-test statistics live
-// in LDS; the rare paths below are real (non-inlined) calls that take the
-// queue length by value and return it, so the hot loop keeps few registers.
+// in LDS; the rare paths take the queue length by value and return it.
 struct WaveState {
     unsigned char* hist; // the workgroup's shared histogram (hist_words counters, kH32)
     uint32_t* qi;        // re-test queue: home index

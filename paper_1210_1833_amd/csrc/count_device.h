@@ -505,7 +505,8 @@ __device__ __forceinline__ void lds_add(uint32_t byte_addr, uint64_t w) {
 
 // Move a 32-bit histogram to the global counts (one wave): every counter is
 // swapped with zero, so increments of the other waves land either in the
-// value moved or in the emptied counter, and none is lost.
+// value moved or in the emptied counter, and none is lost. Out of line: it
+// runs about once per 2^30 increments, and inlined it measured no faster.
 __device__ __attribute__((noinline)) void h32_flush(uint32_t* hist, int words, int copies,
                                                     unsigned long long* counts, int lane) {
     const uint32_t lc = (uint32_t)__builtin_ctz((unsigned)copies);
@@ -604,8 +605,7 @@ __device__ __forceinline__ uint32_t drain_queue(
 // are inlined: most chunks of a clustered catalog queue a pair or two, and an
 // out-of-line call costs its argument moves, the registers the call
 // convention saves (the r-mu and sigma-pi kernels spilled around it) and a
-// stack frame; without calls the r-mu count takes 3 % less time, the others
-// 1 %.
+// stack frame; inlined, the r-mu count takes 3 % less time, the others 1 %.
 template <int MODE, int EST>
 __device__ __forceinline__ uint32_t enqueue_chunk(
     const CountArgs* __restrict__ Pg, unsigned char* hist, uint32_t* qi, uint32_t* qj, uint32_t* qc,

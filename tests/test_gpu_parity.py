@@ -208,6 +208,23 @@ def test_dyadic_lattice_on_edges():
                geom=cute.GEOM_BOX_PERIODIC, L=12.0)
 
 
+def test_dyadic_lattice_midpoint_on_edges():
+    """Lattice points around the z axis, 100 away from the origin: for the
+    pairs placed symmetrically about the axis the midpoint line of sight is
+    exactly z, and pi = |dz| and sigma^2 = dx^2 + dy^2 fall on the sigma, pi,
+    r and mu edges; the canonical FP64 predicates are exact there, so
+    FP32_EDGE must resolve every tie as FP64 and the oracle do."""
+    g = np.random.Generator(np.random.PCG64(19))
+    pts = g.integers(-12, 12, size=(3000, 3)).astype(np.float64) * 0.5
+    pts[:, 2] += 100.0
+    e = np.arange(0, 9) * 0.5
+    check_case("lattice-sigmapi", pts, None, cute.BIN_SIGMAPI, e, e, los=cute.LOS_MIDPOINT)
+    check_case("lattice-rmu-mid", pts, None, cute.BIN_RMU, e, np.array([0.0, 0.25, 0.5, 0.75, 1.0]),
+               los=cute.LOS_MIDPOINT)
+    check_case("lattice-sigmapi-cross", pts[:1500], pts[1500:], cute.BIN_SIGMAPI, e, e,
+               los=cute.LOS_MIDPOINT)
+
+
 def test_periodic_pairs_across_faces():
     L = 100.0
     a = np.array([[0.0, 0.0, 0.0], [99.5, 0.25, 50.0], [50.0, 99.75, 0.5], [0.5, 0.5, 99.5]])

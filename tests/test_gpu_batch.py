@@ -214,3 +214,36 @@ def test_c5_shaped_batch_matches_single_and_jackknife_identity():
         rest, reg, cross = got[2 * len(gm) + 3 * q: 2 * len(gm) + 3 * q + 3]
         assert np.array_equal(rest + reg + cross, dd_base), "region %d" % r
         assert cross.sum() > 0 and reg.sum() > 0
+
+
+def test_batch_lattice_ties_match_oracle():
+    """Dyadic lattices in a periodic box of side 12: many pairs lie exactly on
+    the r and mu edges, so most of the re-test queue's entries cross from one
+    item to the next; every item must equal the oracle for FP64 and
+    FP32_EDGE."""
+    Ll = 12.0
+    e1, e2 = np.arange(0, 9) * 0.5, np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    mono = cute.Binning(cute.BIN_MONO, e1)
+    rmu = cute.Binning(cute.BIN_RMU, e1, e2, los=cute.LOS_Z)
+    omono = oracle.Binning(oracle.MONO, e1, periodic=True, L=Ll)
+    ormu = oracle.Binning(oracle.RMU, e1, e2, los=oracle.LOS_Z, periodic=True, L=Ll)
+    g = np.random.Generator(np.random.PCG64(23))
+    cats = [g.integers(0, 24, size=(n, 3)).astype(np.float64) * 0.5 for n in (700, 1500, 2600)]
+    grids = [cute.build_grid(c, cute.GEOM_BOX_PERIODIC, box_size=Ll, r_max=4.0) for c in cats]
+    mask = (g.random(len(cats[2])) < 0.3).astype(np.uint8)
+    items, expect = [], []
+    for c, gr in zip(cats, grids):
+        for bn, ob in ((mono, omono), (rmu, ormu)):
+            items.append(cute.BatchItem(gr, None, bn))
+            expect.append(oracle.count_pairs(c, None, ob).reshape(-1))
+    items.append(cute.BatchItem(grids[2], None, rmu, mask_a=mask))
+    expect.append(oracle.count_pairs(cats[2][mask == 0], None, ormu).reshape(-1))
+    items.append(cute.BatchItem(grids[0], grids[1], rmu))
+    expect.append(oracle.count_pairs(cats[0], cats[1], ormu).reshape(-1))
+    for prec in EXACT:
+        say("batch lattice: %d items, prec %d" % (len(items), prec))
+        got, st = cute.count_pairs_batched(items, prec, with_stats=True)
+        for k, (gk, ek) in enumerate(zip(got, expect)):
+            assert np.array_equal(gk.reshape(-1), ek), "item %d prec %d" % (k, prec)
+        if prec == cute.PREC_FP32_EDGE:
+            assert st["retests"] > 0

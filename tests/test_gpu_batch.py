@@ -218,9 +218,9 @@ def test_c5_shaped_batch_matches_single_and_jackknife_identity():
 
 def test_batch_lattice_ties_match_oracle():
     """Dyadic lattices in a periodic box of side 12: many pairs lie exactly on
-    the r and mu edges, so most of the re-test queue's entries cross from one
-    item to the next; every item must equal the oracle for FP64 and
-    FP32_EDGE."""
+    the r and mu edges and go through the FP64 re-test, whose queue a wave
+    empties whenever it moves to another item; every item must equal the
+    oracle for FP64 and FP32_EDGE."""
     Ll = 12.0
     e1, e2 = np.arange(0, 9) * 0.5, np.array([0.0, 0.25, 0.5, 0.75, 1.0])
     mono = cute.Binning(cute.BIN_MONO, e1)

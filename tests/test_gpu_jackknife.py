@@ -157,3 +157,26 @@ def test_jackknife_cross_open_boxes_of_different_extent():
     with pytest.raises(cute.CuteError) as ex:
         cute.count_jackknife_cross(gd, reg_d, gd, reg_d, K, bn)
     assert ex.value.status == cute.E_INVALID_ARG
+
+
+def test_jackknife_lattice_ties_match_oracle():
+    """A dyadic lattice in a periodic box of side 12 (pairs exactly on the r
+    and mu edges) split into 8 regions by octant: every leave-one-out count
+    equals the oracle's count of the lattice without that region."""
+    Ll = 12.0
+    e1, e2 = np.arange(0, 9) * 0.5, np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    g = np.random.Generator(np.random.PCG64(29))
+    pts = g.integers(0, 24, size=(2500, 3)).astype(np.float64) * 0.5
+    region = ((pts[:, 0] >= 6.0).astype(np.int32) + 2 * (pts[:, 1] >= 6.0) + 4 * (pts[:, 2] >= 6.0)).astype(np.int32)
+    grid = cute.build_grid(pts, cute.GEOM_BOX_PERIODIC, box_size=Ll, r_max=4.0)
+    for bn, ob in ((cute.Binning(cute.BIN_MONO, e1), oracle.Binning(oracle.MONO, e1, periodic=True, L=Ll)),
+                   (cute.Binning(cute.BIN_RMU, e1, e2, los=cute.LOS_Z),
+                    oracle.Binning(oracle.RMU, e1, e2, los=oracle.LOS_Z, periodic=True, L=Ll))):
+        want_total = oracle.count_pairs(pts, None, ob).reshape(-1)
+        for prec in EXACT:
+            say("jackknife lattice, %d bins, prec %d" % (bn.nbins, prec))
+            total, jack = cute.count_jackknife(grid, region, 8, bn, prec)
+            np.testing.assert_array_equal(total.reshape(-1), want_total)
+            for k in range(8):
+                want = oracle.count_pairs(pts[region != k], None, ob).reshape(-1)
+                np.testing.assert_array_equal(jack[k].reshape(-1), want, err_msg="region %d" % k)

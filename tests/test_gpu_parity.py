@@ -169,6 +169,21 @@ def test_theta_linear_bins_large_angles():
     check_case("theta-fullsky-lin", v, None, cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
 
 
+def test_theta_axis_vectors_on_the_right_angle_edge():
+    """Copies of the six axis unit vectors: their pairs lie at exactly 0, 90
+    or 180 degrees, and 90 degrees is a bin edge, so FP32_EDGE must re-test
+    them and decide each as FP64 and the oracle do; random unit vectors fill
+    the other bins."""
+    g = np.random.Generator(np.random.PCG64(31))
+    axes = np.concatenate([np.eye(3), -np.eye(3)])
+    v = g.normal(size=(2000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    pts = np.concatenate([np.repeat(axes, 40, axis=0), v])
+    e = np.deg2rad(np.array([0.0, 30.0, 60.0, 90.0, 120.0]))
+    check_case("theta-axis-ties", pts, None, cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
+    check_case("theta-axis-ties-cross", pts[:240], v[:500], cute.BIN_THETA, e, geom=cute.GEOM_SPHERE)
+
+
 # ---------------------------------------------------------------------------
 # Edge cases
 # ---------------------------------------------------------------------------

@@ -247,3 +247,15 @@ def test_xi_estimate_exact_arithmetic_guard(lib):
         assert lib.cute_xi_estimate(cute.EST_LS, c["dd"].ctypes.data, c["dr"].ctypes.data,
                                     c["rr"].ctypes.data, 10, 10, ctypes.byref(good.c()), 0.0,
                                     pxi) == cute.E_INVALID_ARG, name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: any other --gpus exits with status 2 and a
+    message, before it touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "8"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
